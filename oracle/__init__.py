@@ -1,0 +1,209 @@
+"""FP64 CPU oracle for the FOS photon-transport method -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The HIP product library never loads it
+and shares no source with it.
+
+The numerical work is in ``fos_oracle.c`` (plain C99, double precision,
+POSIX threads across items); ``mlp.py`` holds the numpy FP64 surrogate oracle.
+This module only marshals arguments through ctypes.
+
+Parity status (each function's pins live in ``tests/test_oracle_*.py``):
+  philox, fresnel, hg_cos, walk, walk_batch, mie_coeffs, mie_sphere,
+  layer_optics, optics_batch -- pinned (published test vectors, closed forms,
+  limits, invariants, independent special-function evaluation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_uint32, c_uint64
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fos_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+N_TALLY = 6
+TALLY_NAMES = ("r_spec", "r_diff", "absorbed", "transmitted", "capped", "steps")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE semantics kept)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        d = POINTER(c_double)
+        u64p = POINTER(c_uint64)
+        lib.orc_philox4x32_10.argtypes = [POINTER(c_uint32), POINTER(c_uint32), POINTER(c_uint32)]
+        lib.orc_uniforms.argtypes = [c_uint64, c_uint32, c_uint32, c_uint64, d]
+        lib.orc_fresnel.argtypes = [c_double] * 4
+        lib.orc_fresnel.restype = c_double
+        lib.orc_hg_cos.argtypes = [c_double, c_double]
+        lib.orc_hg_cos.restype = c_double
+        lib.orc_walk.argtypes = [c_int, d, d, d, d, d, c_double, c_double, c_double, c_double,
+                                 c_uint32, c_uint64, c_uint64, c_uint64, c_uint64, u64p]
+        lib.orc_walk_batch.argtypes = [c_int, c_int, POINTER(c_int32), d, d, d, d, d, d, d, d, d,
+                                       u64p, POINTER(c_uint32), c_uint64, c_uint64, c_int, u64p]
+        lib.orc_walk_batch.restype = c_int
+        lib.orc_mie_coeffs.argtypes = [c_double, c_double, c_double, c_double, c_int, d, d]
+        lib.orc_mie_nmax.argtypes = [c_double]
+        lib.orc_mie_nmax.restype = c_int
+        lib.orc_gamma.argtypes = [c_double]
+        lib.orc_gamma.restype = c_double
+        lib.orc_mie_sphere.argtypes = [c_double] * 6 + [d]
+        lib.orc_layer_optics.argtypes = [c_double, c_double, c_double, c_int, d, d, d, d, d]
+        lib.orc_optics_batch.argtypes = [c_int, d, d, d, POINTER(c_int64), d, d, d, d, c_int, d]
+        lib.orc_optics_batch.restype = c_int
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+# ---------------------------------------------------------------------------
+# generator
+# ---------------------------------------------------------------------------
+
+def philox(ctr, key):
+    """Philox4x32-10 of a 4-word counter and 2-word key -> 4 uint32."""
+    c = (c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (c_uint32 * 4)()
+    _load().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniforms(photon: int, step: int, stream: int, seed: int):
+    """The four 24-bit uniforms U0..U3 of (photon, step, stream) under seed."""
+    u = (c_double * 4)()
+    _load().orc_uniforms(photon, step, stream, seed, u)
+    return list(u)
+
+
+# ---------------------------------------------------------------------------
+# physics pieces
+# ---------------------------------------------------------------------------
+
+def fresnel(ci: float, ni: float, nt: float, kt: float = 0.0) -> float:
+    return _load().orc_fresnel(ci, ni, nt, kt)
+
+
+def hg_cos(g: float, u: float) -> float:
+    return _load().orc_hg_cos(g, u)
+
+
+def walk(mu_s, mu_a, g, n, t, n_upper=1.0, n_lower=1.0, k_lower=0.0, mu0=1.0, photons=1000,
+         seed=1, stream=0, photon_begin=0, max_steps=1 << 40):
+    """One stack, one thread.  Returns the 6 tallies as a uint64 array."""
+    mu_s, mu_a, g, n, t = (_f64(np.atleast_1d(x)) for x in (mu_s, mu_a, g, n, t))
+    L = len(mu_s)
+    out = np.zeros(N_TALLY, np.uint64)
+    _load().orc_walk(L, _dp(mu_s), _dp(mu_a), _dp(g), _dp(n), _dp(t), n_upper, n_lower, k_lower,
+                     mu0, stream, seed, photon_begin, photon_begin + photons, max_steps,
+                     out.ctypes.data_as(POINTER(c_uint64)))
+    return out
+
+
+def walk_batch(n_layers, mu_s, mu_a, g, n_layer, thickness, n_upper, n_lower, k_lower, mu0,
+               photons, seed, streams=None, max_steps=1 << 40, n_threads=None):
+    """Many items, threaded.  Per-layer arrays are [I, L]; per-item [I].
+    Returns uint64 tallies [I, 6]."""
+    n_layers = np.ascontiguousarray(n_layers, np.int32)
+    I = len(n_layers)
+    mu_s = _f64(mu_s).reshape(I, -1)
+    L = mu_s.shape[1]
+    arrs = [_f64(a).reshape(I, L) for a in (mu_s, mu_a, g, n_layer, thickness)]
+    items = [_f64(a).reshape(I) for a in (n_upper, n_lower, k_lower, mu0)]
+    photons = np.ascontiguousarray(photons, np.uint64)
+    st = None if streams is None else np.ascontiguousarray(streams, np.uint32)
+    out = np.zeros((I, N_TALLY), np.uint64)
+    nt = n_threads or default_threads()
+    rc = _load().orc_walk_batch(
+        I, L, n_layers.ctypes.data_as(POINTER(c_int32)), *[_dp(a) for a in arrs],
+        *[_dp(a) for a in items], photons.ctypes.data_as(POINTER(c_uint64)),
+        None if st is None else st.ctypes.data_as(POINTER(c_uint32)), seed, max_steps, nt,
+        out.ctypes.data_as(POINTER(c_uint64)))
+    if rc != 0:
+        raise ValueError("orc_walk_batch rejected its arguments")
+    return out
+
+
+def mie_nmax(y_abs: float) -> int:
+    return _load().orc_mie_nmax(y_abs)
+
+
+def gamma_term(alpha: float) -> float:
+    return _load().orc_gamma(alpha)
+
+
+def mie_coeffs(x: complex, m: complex, nmax: int):
+    """a_n, b_n for n = 1..nmax (complex numpy arrays)."""
+    a = np.zeros(2 * nmax); b = np.zeros(2 * nmax)
+    _load().orc_mie_coeffs(x.real, x.imag, m.real, m.imag, nmax, _dp(a), _dp(b))
+    return a[0::2] + 1j * a[1::2], b[0::2] + 1j * b[1::2]
+
+
+def mie_sphere(lam, n_m, k_m, n_p, k_p, r):
+    """(q_ext, q_sca, g, nmax) of one sphere, eqs. (1)-(12), (15)."""
+    o = np.zeros(4)
+    _load().orc_mie_sphere(lam, n_m, k_m, n_p, k_p, r, _dp(o))
+    return o[0], o[1], o[2], int(o[3])
+
+
+def layer_optics(lam, n_m, k_m, n_p, k_p, r, f):
+    """(mu_s, mu_a, g) of one layer at one wavelength, eqs. (13)-(20)."""
+    n_p, k_p, r, f = (_f64(np.atleast_1d(x)) for x in (n_p, k_p, r, f))
+    o = np.zeros(3)
+    _load().orc_layer_optics(lam, n_m, k_m, len(n_p), _dp(n_p), _dp(k_p), _dp(r), _dp(f), _dp(o))
+    return o[0], o[1], o[2]
+
+
+def optics_batch(req, n_threads=None):
+    """Optics of every cell of a workloads.optics_request(); returns [C, 3]."""
+    C = int(req["cells"])
+    out = np.zeros((C, 3))
+    offs = np.ascontiguousarray(req["offsets"], np.int64)
+    arrs = [_f64(req[k]) for k in ("lam", "n_m", "k_m")]
+    parts = [_f64(req[k]) for k in ("n_p", "k_p", "r", "f")]
+    _load().orc_optics_batch(C, *[_dp(a) for a in arrs], offs.ctypes.data_as(POINTER(c_int64)),
+                             *[_dp(a) for a in parts], n_threads or default_threads(), _dp(out))
+    return out
+
+
+def workload_optics(wl, n_threads=None):
+    """(mu_s, mu_a, g) arrays [I, L] for a workloads.Workload."""
+    from paper_2409_00165_amd import workloads as W  # input recipes only
+    req = W.optics_request(wl)
+    o = optics_batch(req, n_threads)
+    L = req["max_layers"]
+    return o[:, 0].reshape(-1, L), o[:, 1].reshape(-1, L), o[:, 2].reshape(-1, L)

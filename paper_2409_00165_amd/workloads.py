@@ -1,0 +1,311 @@
+"""Seeded synthetic workload recipes (inputs only).
+
+This module describes *what* is simulated: wavelength grids, the analytic
+complex indices of the two synthetic particle species and of the matrix,
+particle-size bins, layer stacks, boundary media and photon budgets.  It holds
+none of the method's arithmetic (no Mie theory, no effective-medium formulas,
+no photon transport), so both the GPU library and the CPU oracle can consume
+the same inputs without sharing any computation.
+
+Units follow the paper: lengths in micrometres, coefficients in 1/micrometre
+(Input section, material-file description).  Volume fractions are fractions,
+not percentages (the paper's input file takes percentages; eqs. (13)-(20) use
+fractions).
+
+Workloads
+---------
+* ``single_slab_23``   : 23 wavelengths 0.3-2.5 um, one 50 um slab, species A
+                         monodisperse r = 0.2 um at f = 0.10, 1e4 photons.
+* ``two_species_500``  : 500 log-spaced wavelengths 0.3-16 um, one 500 um slab,
+                         species A (f = 0.08) and B (f = 0.05), log-normal radii
+                         binned into 20 sizes, matrix k = 1e-4, 1e6 photons.
+* ``stacks_3layer``    : N designs of three random layers on an absorbing
+                         substrate (3.5 + 0.01i), 100 wavelengths, uneven
+                         photon budgets log-uniform in [1e4, 1e6].
+* ``paint_1layer``     : single-layer designs for the surrogate sweep.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# wavelength grids
+# ----------------------------------------------------------------------------
+
+
+def grid_linear(start: float, stop: float, step: float) -> np.ndarray:
+    """Start:Interval:End grid as in the input-file header (both ends kept)."""
+    n = int(round((stop - start) / step)) + 1
+    return start + step * np.arange(n, dtype=np.float64)
+
+
+def grid_log(lo: float, hi: float, n: int) -> np.ndarray:
+    """lambda_i = lo * (hi/lo)^(i/(n-1)), endpoints included."""
+    i = np.arange(n, dtype=np.float64)
+    return lo * (hi / lo) ** (i / (n - 1))
+
+
+# ----------------------------------------------------------------------------
+# materials (synthetic; the paper's material files are not available)
+# ----------------------------------------------------------------------------
+
+
+def species_a_index(lam: np.ndarray):
+    """Synthetic high-index pigment: n = 2.5 + 0.1/lambda^2, k = 1e-3."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return 2.5 + 0.1 / lam**2, np.full_like(lam, 1e-3)
+
+
+def species_b_index(lam: np.ndarray):
+    """Synthetic silica-like filler: n = 1.45 and a Lorentzian absorption
+    band centred at 9 um, peak k = 0.5, full width at half maximum 0.3 um."""
+    lam = np.asarray(lam, dtype=np.float64)
+    hw = 0.15
+    return np.full_like(lam, 1.45), 0.5 * hw**2 / ((lam - 9.0) ** 2 + hw**2)
+
+
+SPECIES = {"A": species_a_index, "B": species_b_index}
+
+
+def lognormal_bins(r_med: float, sigma_ln: float, n_bins: int = 20, span: float = 3.0):
+    """Volume-fraction weights of a log-normal radius distribution.
+
+    Equal-width bins in ln r over [ln r_med - span*sigma, ln r_med + span*sigma];
+    the representative radius is exp(bin centre) and the weight is the normal
+    probability mass of the bin, renormalised to sum to one.  sigma -> 0 gives a
+    single size.  Returns (radii, weights).
+    """
+    if sigma_ln <= 0.0:
+        return np.array([r_med]), np.array([1.0])
+    mu = math.log(r_med)
+    edges = np.linspace(mu - span * sigma_ln, mu + span * sigma_ln, n_bins + 1)
+    cdf = np.array([0.5 * (1.0 + math.erf((e - mu) / (sigma_ln * math.sqrt(2.0)))) for e in edges])
+    w = np.diff(cdf)
+    w = w / w.sum()
+    centres = 0.5 * (edges[:-1] + edges[1:])
+    return np.exp(centres), w
+
+
+# ----------------------------------------------------------------------------
+# problem description
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class Particles:
+    """One particle population inside a layer: a species evaluated on the
+    wavelength grid, a list of radii and their volume fractions."""
+
+    species: str
+    radii: np.ndarray        # [n_sizes] um
+    fractions: np.ndarray    # [n_sizes] volume fractions (sum = population f)
+
+
+@dataclass
+class Layer:
+    thickness: float                 # um
+    n_matrix: float                  # real part of matrix index
+    k_matrix: float                  # imaginary part of matrix index
+    particles: List[Particles] = field(default_factory=list)
+
+
+@dataclass
+class Design:
+    layers: List[Layer]
+    n_upper: float = 1.0
+    n_lower: float = 1.0
+    k_lower: float = 0.0
+    mu0: float = 1.0
+    photons: int = 10_000
+
+
+@dataclass
+class Workload:
+    name: str
+    wavelengths: np.ndarray   # [n_lambda]
+    designs: List[Design]
+
+    @property
+    def n_items(self) -> int:
+        return len(self.designs) * len(self.wavelengths)
+
+    @property
+    def max_layers(self) -> int:
+        return max(len(d.layers) for d in self.designs)
+
+
+def particle_table(wl: Workload, design: int, layer: int, lam_index: int):
+    """Flat per-(layer, wavelength) particle list: arrays (n_p, k_p, r, f)."""
+    lay = wl.designs[design].layers[layer]
+    lam = wl.wavelengths[lam_index : lam_index + 1]
+    n_p, k_p, r, f = [], [], [], []
+    for pop in lay.particles:
+        n, k = SPECIES[pop.species](lam)
+        for ri, fi in zip(pop.radii, pop.fractions):
+            n_p.append(n[0]); k_p.append(k[0]); r.append(ri); f.append(fi)
+    return (np.array(n_p), np.array(k_p), np.array(r), np.array(f))
+
+
+# ----------------------------------------------------------------------------
+# the concrete workloads
+# ----------------------------------------------------------------------------
+
+
+def single_slab_23(photons: int = 10_000) -> Workload:
+    """23 wavelengths 0.3..2.5 um step 0.1; 50 um slab, n_m = 1.5, air on
+    both sides, species A monodisperse r = 0.2 um at f = 0.10, normal
+    incidence."""
+    lam = grid_linear(0.3, 2.5, 0.1)
+    pop = Particles("A", np.array([0.2]), np.array([0.10]))
+    d = Design([Layer(50.0, 1.5, 0.0, [pop])], photons=photons)
+    return Workload("single_slab_23", lam, [d])
+
+
+def two_species_500(photons: int = 1_000_000, n_lambda: int = 500) -> Workload:
+    """500 log-spaced wavelengths 0.3..16 um; 500 um slab, matrix
+    1.5 + 1e-4 i; species A (f = 0.08) and B (f = 0.05), each log-normal with
+    median 0.25 um and sigma_ln = 0.3 in 20 bins; air on both sides."""
+    lam = grid_log(0.3, 16.0, n_lambda)
+    r, w = lognormal_bins(0.25, 0.3, 20)
+    pops = [Particles("A", r, 0.08 * w), Particles("B", r, 0.05 * w)]
+    d = Design([Layer(500.0, 1.5, 1e-4, pops)], photons=photons)
+    return Workload("two_species_500", lam, [d])
+
+
+def stacks_3layer(n_designs: int = 4096, n_lambda: int = 100, seed: int = 20240900,
+                  photons_lo: float = 1e4, photons_hi: float = 1e6) -> Workload:
+    """Three-layer stacks on an absorbing substrate (3.5 + 0.01i).
+
+    Per layer: thickness ~ U[5, 500] um, volume fraction ~ U[0.01, 0.3],
+    median radius ~ U[0.05, 1] um (log-normal sigma_ln 0.3, 20 bins), species
+    drawn from {A, B}, matrix n ~ U[1.3, 1.7] with k = 1e-4.  Upper medium air.
+    One photon budget per design, log-uniform in [photons_lo, photons_hi].
+    """
+    rng = np.random.default_rng(seed)
+    lam = grid_log(0.3, 16.0, n_lambda)
+    designs = []
+    for _ in range(n_designs):
+        layers = []
+        for _l in range(3):
+            t = rng.uniform(5.0, 500.0)
+            f = rng.uniform(0.01, 0.3)
+            rm = rng.uniform(0.05, 1.0)
+            sp = "A" if rng.uniform() < 0.5 else "B"
+            nm = rng.uniform(1.3, 1.7)
+            r, w = lognormal_bins(rm, 0.3, 20)
+            layers.append(Layer(t, nm, 1e-4, [Particles(sp, r, f * w)]))
+        n_ph = int(round(math.exp(rng.uniform(math.log(photons_lo), math.log(photons_hi)))))
+        designs.append(Design(layers, n_upper=1.0, n_lower=3.5, k_lower=0.01, photons=n_ph))
+    return Workload("stacks_3layer", lam, designs)
+
+
+def paint_1layer(n_designs: int, n_lambda: int = 200, seed: int = 20240901,
+                 photons: int = 100_000) -> Workload:
+    """Single-layer paint designs in air (the surrogate's domain): the
+    per-layer distribution of ``stacks_3layer`` with one layer."""
+    rng = np.random.default_rng(seed)
+    lam = grid_log(0.3, 16.0, n_lambda)
+    designs = []
+    for _ in range(n_designs):
+        t = rng.uniform(5.0, 500.0)
+        f = rng.uniform(0.01, 0.3)
+        rm = rng.uniform(0.05, 1.0)
+        sp = "A" if rng.uniform() < 0.5 else "B"
+        nm = rng.uniform(1.3, 1.7)
+        r, w = lognormal_bins(rm, 0.3, 20)
+        designs.append(Design([Layer(t, nm, 1e-4, [Particles(sp, r, f * w)])], photons=photons))
+    return Workload("paint_1layer", lam, designs)
+
+
+# ----------------------------------------------------------------------------
+# flat item arrays for the transport step (inputs only, optics supplied)
+# ----------------------------------------------------------------------------
+
+
+def item_geometry(wl: Workload):
+    """Per-item geometry arrays in the order design-major, wavelength-minor.
+
+    Returns a dict of numpy arrays: n_layers [I], thickness [I, L],
+    n_layer [I, L], n_upper, n_lower, k_lower, mu0 [I], photons [I] (uint64).
+    Layers beyond a design's count are padded with zeros.
+    """
+    L = wl.max_layers
+    nl = len(wl.wavelengths)
+    I = wl.n_items
+    out = {
+        "n_layers": np.zeros(I, np.int32),
+        "thickness": np.zeros((I, L), np.float64),
+        "n_layer": np.zeros((I, L), np.float64),
+        "n_upper": np.zeros(I, np.float64),
+        "n_lower": np.zeros(I, np.float64),
+        "k_lower": np.zeros(I, np.float64),
+        "mu0": np.zeros(I, np.float64),
+        "photons": np.zeros(I, np.uint64),
+    }
+    for d, des in enumerate(wl.designs):
+        s = slice(d * nl, (d + 1) * nl)
+        out["n_layers"][s] = len(des.layers)
+        for l, lay in enumerate(des.layers):
+            out["thickness"][s, l] = lay.thickness
+            out["n_layer"][s, l] = lay.n_matrix
+        out["n_upper"][s] = des.n_upper
+        out["n_lower"][s] = des.n_lower
+        out["k_lower"][s] = des.k_lower
+        out["mu0"][s] = des.mu0
+        out["photons"][s] = des.photons
+    return out
+
+
+def optics_request(wl: Workload):
+    """Flatten the optics inputs of every (design, layer, wavelength) cell.
+
+    Returns a dict with per-cell arrays ``lam``, ``n_m``, ``k_m`` [C] and a
+    CSR particle list: ``offsets`` [C+1], ``n_p``, ``k_p``, ``r``, ``f`` [P].
+    Cells are ordered item-major (design, wavelength) then layer, i.e. cell
+    ``item * L + layer`` with L = max_layers; padded layers have no particles
+    and zero matrix absorption.
+    """
+    L = wl.max_layers
+    lamv = wl.wavelengths
+    nl = len(lamv)
+    C = wl.n_items * L
+    lam = np.zeros(C); n_m = np.ones(C); k_m = np.zeros(C)
+    counts = np.zeros(C, np.int64)
+    # per (design, layer): species index arrays over lambda
+    chunks_np, chunks_kp, chunks_r, chunks_f = [], [], [], []
+    for d, des in enumerate(wl.designs):
+        for l in range(L):
+            lay = des.layers[l] if l < len(des.layers) else None
+            cells = (d * nl + np.arange(nl)) * L + l
+            lam[cells] = lamv
+            if lay is None:
+                continue
+            n_m[cells] = lay.n_matrix
+            k_m[cells] = lay.k_matrix
+            per = sum(len(p.radii) for p in lay.particles)
+            counts[cells] = per
+            npl = np.zeros((nl, per)); kpl = np.zeros((nl, per))
+            rl = np.zeros(per); fl = np.zeros(per)
+            j = 0
+            for pop in lay.particles:
+                n, k = SPECIES[pop.species](lamv)
+                m = len(pop.radii)
+                npl[:, j:j + m] = n[:, None]; kpl[:, j:j + m] = k[:, None]
+                rl[j:j + m] = pop.radii; fl[j:j + m] = pop.fractions
+                j += m
+            chunks_np.append((cells, npl)); chunks_kp.append(kpl)
+            chunks_r.append(np.broadcast_to(rl, (nl, per))); chunks_f.append(np.broadcast_to(fl, (nl, per)))
+    offsets = np.zeros(C + 1, np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    P = int(offsets[-1])
+    n_p = np.zeros(P); k_p = np.zeros(P); r = np.zeros(P); f = np.zeros(P)
+    for (cells, npl), kpl, rl, fl in zip(chunks_np, chunks_kp, chunks_r, chunks_f):
+        per = npl.shape[1]
+        idx = offsets[cells][:, None] + np.arange(per)[None, :]
+        n_p[idx] = npl; k_p[idx] = kpl; r[idx] = rl; f[idx] = fl
+    return {"lam": lam, "n_m": n_m, "k_m": k_m, "offsets": offsets,
+            "n_p": n_p, "k_p": k_p, "r": r, "f": f, "cells": C, "max_layers": L}

@@ -1,0 +1,185 @@
+/*
+ * fos_mc.h -- C ABI of libfos_mc: Monte Carlo photon transport through
+ * particle-laden multi-layer slabs on AMD Instinct MI355X (gfx950).
+ *
+ * The operation follows the paper "FOS: Fast Optical Spectrum calculations
+ * of nanoparticle media" (arXiv 2409.00165):
+ *   - inputs per wavelength are the effective scattering coefficient mu_s,
+ *     absorption coefficient mu_a and asymmetry parameter g of every layer
+ *     (Methodology, Scattering properties, eqs. (13)-(20); the four-column
+ *     material file of the Input section carries exactly these), layer
+ *     thicknesses with "Layer 1" on top, the real matrix index of every layer
+ *     and the upper/lower boundary media (Input section: air, n = 1, unless
+ *     set; the Monte Carlo method accepts any lower medium, conductors
+ *     included -- Methodology, Photon transport);
+ *   - outputs are photon counts reflected, absorbed and transmitted per
+ *     wavelength (Methodology, Photon transport: an MCML-style walk that
+ *     tracks only depth and the direction cosine to the surface normal;
+ *     step size from the extinction, scatter-versus-absorb from the albedo,
+ *     new direction from g; Fresnel reflection at every boundary using the
+ *     matrix index).
+ *
+ * Units: lengths in micrometres, coefficients in 1/micrometre.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked DEVICE are caller-owned device memory on the context's
+ *     device; pointers marked HOST are host memory.  The library never frees
+ *     or keeps caller memory beyond the call's completion on the stream.
+ *   - `hip_stream` is a hipStream_t (NULL = the legacy default stream).
+ *   - Status codes only; no exception crosses the ABI.  After a failure
+ *     fos_last_error(ctx) describes it (valid until the next call on ctx).
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef FOS_MC_H
+#define FOS_MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FOS_ABI_VERSION 1
+#define FOS_MAX_LAYERS 8
+
+/* tally slots per item, in this order, uint64 each */
+#define FOS_TALLY_R_SPECULAR   0  /* reflected at the first face on entry       */
+#define FOS_TALLY_R_DIFFUSE    1  /* left through the top face after entering   */
+#define FOS_TALLY_ABSORBED     2  /* absorbed inside a layer                    */
+#define FOS_TALLY_TRANSMITTED  3  /* entered the lower medium                   */
+#define FOS_TALLY_CAPPED       4  /* stopped by the per-photon step cap         */
+#define FOS_TALLY_STEPS        5  /* photon-steps taken (free-path iterations)  */
+#define FOS_N_TALLY            6
+
+typedef enum {
+    FOS_OK = 0,
+    FOS_E_INVALID_ARG = 1,
+    FOS_E_UNSUPPORTED = 2,
+    FOS_E_DEVICE = 3,
+    FOS_E_OUT_OF_MEMORY = 4,
+    FOS_E_INTERNAL = 5,
+    FOS_E_NOT_PREPARED = 6
+} fos_status;
+
+typedef struct fos_ctx fos_ctx;
+
+/* Library ABI version (FOS_ABI_VERSION of the build). */
+int fos_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* fos_status_string(fos_status s);
+
+/* Create a context bound to HIP device `hip_device`.  The context owns all
+ * internal device scratch (packed item tables, work cursors).  Fails with
+ * FOS_E_DEVICE if the device is absent or not gfx950. */
+fos_status fos_create(int hip_device, fos_ctx** out);
+
+/* Release a context and its scratch; NULL-safe.  Synchronises the device
+ * before freeing. */
+void fos_destroy(fos_ctx* ctx);
+
+/* Message for the last failing call on ctx ("" if none). */
+const char* fos_last_error(const fos_ctx* ctx);
+
+/* ------------------------------------------------------------------------- */
+/* Monte Carlo transport                                                      */
+/* ------------------------------------------------------------------------- */
+
+/* One batch of independent items.  An item is one (design, wavelength)
+ * pair: a stack of n_layers[i] layers between an upper medium of real index
+ * n_upper[i] (light arrives from there at incidence cosine mu0[i]) and a
+ * lower half-space of complex index n_lower[i] + i k_lower[i].  Per-layer
+ * arrays are row-major [n_items][max_layers]; entries beyond n_layers[i] are
+ * ignored.  All pointers are DEVICE.
+ *
+ * Valid values: 1 <= n_layers <= max_layers <= FOS_MAX_LAYERS; mu_s, mu_a
+ * >= 0 and finite (mu_s + mu_a = 0, a clear layer, is allowed); -1 <= g <= 1;
+ * n_layer >= 1; thickness > 0 and finite; n_upper >= 1; n_lower > 0;
+ * k_lower >= 0; 0 < mu0 <= 1; photons >= 0 (an item with 0 photons
+ * yields zero tallies). */
+typedef struct {
+    int32_t n_items;
+    int32_t max_layers;
+    const int32_t* n_layers;   /* [n_items]              */
+    const float* mu_s;         /* [n_items * max_layers] */
+    const float* mu_a;         /* [n_items * max_layers] */
+    const float* g;            /* [n_items * max_layers] */
+    const float* n_layer;      /* [n_items * max_layers] real matrix index */
+    const float* thickness;    /* [n_items * max_layers] */
+    const float* n_upper;      /* [n_items] */
+    const float* n_lower;      /* [n_items] */
+    const float* k_lower;      /* [n_items] */
+    const float* mu0;          /* [n_items] */
+    const uint64_t* photons;   /* [n_items] */
+} fos_mc_problem;
+
+/* Launch knobs of the persistent walk kernel; a zero field takes the
+ * context's current default (set by fos_mc_autotune, else built-in). */
+typedef struct {
+    int32_t block_size;     /* threads per workgroup, multiple of 64, 64..1024   */
+    int32_t refill_min;     /* refill a wave when >= this many lanes idle, 1..64 */
+    int32_t chunk;          /* photons a wave claims from the queue at once      */
+    int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu             */
+    uint64_t max_steps;     /* per-photon step cap (photons beyond it -> CAPPED) */
+} fos_mc_launch;
+
+/* Validate `problem` and pack it into the context's device item table
+ * (per item: entry Fresnel reflectance and refracted cosine; per layer:
+ * extinction, albedo, Henyey-Greenstein constants, interface index ratios).
+ * Runs a validation kernel on `hip_stream` and synchronises that stream to
+ * read its verdict; an invalid problem returns FOS_E_INVALID_ARG naming the
+ * first offending item and field, and leaves caller memory untouched.  The
+ * packed table stays in the context until the next prepare. */
+fos_status fos_mc_prepare(fos_ctx* ctx, const fos_mc_problem* problem, void* hip_stream);
+
+/* Walk every photon of the prepared problem and write the tallies.
+ * `tallies` is DEVICE uint64 [n_items * FOS_N_TALLY], overwritten.  The
+ * random stream of photon p of item i under `seed` is Philox4x32-10 with
+ * counter (p lo, p hi, step, i) and key (seed lo, seed hi), so tallies are
+ * bit-identical for every launch configuration, chunking and scheduling.
+ * Asynchronous on `hip_stream`; allocates nothing, never synchronises, and
+ * may be captured into a HIP graph.  `launch` may be NULL. */
+fos_status fos_mc_execute(fos_ctx* ctx, uint64_t seed, const fos_mc_launch* launch,
+                          uint64_t* tallies, void* hip_stream);
+
+/* fos_mc_prepare followed by fos_mc_execute. */
+fos_status fos_mc_run(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
+                      const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
+
+/* Number of items of the prepared problem (0 if none). */
+int32_t fos_mc_prepared_items(const fos_ctx* ctx);
+
+/* Current launch defaults of the context (HOST out). */
+fos_status fos_mc_get_launch(const fos_ctx* ctx, fos_mc_launch* out);
+
+/* Set the context's launch defaults; fields equal to 0 keep their value. */
+fos_status fos_mc_set_launch(fos_ctx* ctx, const fos_mc_launch* launch);
+
+/* Raw Philox4x32-10 words for testing the generator: out[4*j + w] =
+ * word w of counter (p lo, p hi, step, stream) with p = photon[j],
+ * key (seed lo, seed hi).  photon, step, stream DEVICE [n]; out DEVICE
+ * [4n].  Asynchronous on hip_stream. */
+fos_status fos_philox_words(fos_ctx* ctx, int32_t n, const uint64_t* photon, const uint32_t* step,
+                            const uint32_t* stream, uint64_t seed, uint32_t* out, void* hip_stream);
+
+/* Fresnel reflectance exactly as the walk evaluates it, for testing:
+ * out[j] = unpolarised reflectance from real index ni[j] into nt[j] +
+ * i kt[j] at incidence cosine c[j] (Methodology, Photon transport: Fresnel
+ * at the boundaries with the matrix index; any lower medium, conductors
+ * included).  All arrays DEVICE [n]. */
+fos_status fos_eval_fresnel(fos_ctx* ctx, int32_t n, const float* c, const float* ni, const float* nt,
+                            const float* kt, float* out, void* hip_stream);
+
+/* Henyey-Greenstein polar cosine exactly as the walk samples it, for
+ * testing: out[j] = cos theta drawn with asymmetry g[j] from the uniform
+ * u01[j] in [0,1) (the new direction angle from g, Methodology, Photon
+ * transport).  All arrays DEVICE [n]. */
+fos_status fos_eval_hg(fos_ctx* ctx, int32_t n, const float* g, const float* u01, float* out,
+                       void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOS_MC_H */

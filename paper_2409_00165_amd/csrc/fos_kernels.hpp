@@ -1,0 +1,58 @@
+// fos_kernels.hpp -- kernel argument blocks and launchers shared by the
+// kernels and the host runtime of libfos_mc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fos {
+
+enum ErrCode : int {
+    kErrNLayers = 1,
+    kErrMuS = 2,
+    kErrMuA = 3,
+    kErrG = 4,
+    kErrNLayer = 5,
+    kErrThickness = 6,
+    kErrNUpper = 7,
+    kErrNLower = 8,
+    kErrKLower = 9,
+    kErrMu0 = 10,
+};
+
+struct PackArgs {
+    int n_items, max_layers;
+    const int32_t* n_layers;
+    const float *mu_s, *mu_a, *g, *n_layer, *thickness;
+    const float *n_upper, *n_lower, *k_lower, *mu0;
+    const uint64_t* photons;
+    float4* table;
+    unsigned long long* err;
+};
+
+struct WalkArgs {
+    const float4* table;
+    int n_items, max_layers, rec_f4;
+    unsigned long long* cursors;
+    uint32_t* cur_item;
+    unsigned long long* tallies;
+    uint64_t seed;
+    uint32_t max_steps;
+    int chunk;
+    int refill_min;
+};
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t st);
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
+                        int n_items, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
+hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st);
+size_t walk_lds_bytes(int block_size, int max_layers);
+hipError_t launch_philox_words(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
+                               uint64_t seed, uint32_t* out, hipStream_t st);
+hipError_t launch_eval_fresnel(int n, const float* c, const float* ni, const float* nt, const float* kt,
+                               float* out, hipStream_t st);
+hipError_t launch_eval_hg(int n, const float* g, const float* u01, float* out, hipStream_t st);
+
+}  // namespace fos

@@ -1,0 +1,508 @@
+// mc_kernels.hip -- gfx950 kernels of the Monte Carlo photon walk.
+//
+//   pack_items    : validate one item per thread and write its packed record
+//                   (entry Fresnel reflectance, refracted cosine, per-layer
+//                   extinction, albedo, HG constants, interface ratios).
+//   reset_run     : zero the caller's tallies and the work cursors.
+//   walk          : the persistent photon walk (one photon per lane).
+//   philox_words / eval_fresnel / eval_hg : thin kernels exposing the device
+//                   building blocks to the test-suite.
+//
+// The walk follows the paper's Monte Carlo transport (Methodology, Photon
+// transport): per photon only the depth z and the direction cosine mu_z to
+// the surface normal are tracked; the free path follows from the extinction
+// coefficient, scatter-versus-absorb from the albedo, the new direction from
+// the Henyey-Greenstein asymmetry g (MCML, ref. [45]); every boundary
+// reflects or refracts by unpolarised Fresnel with the matrix index, and the
+// lower medium may be absorbing (complex index).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fos_device.hpp"
+#include "fos_kernels.hpp"
+
+namespace fos {
+
+// ---------------------------------------------------------------------------
+// pack + validate
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool finite_(float x) { return isfinite(x); }
+
+__device__ __forceinline__ void report(unsigned long long* err, int item, int layer, int code)
+{
+    unsigned long long w = ((unsigned long long)(uint32_t)item << 16) |
+                           ((unsigned long long)(layer & 0xFF) << 8) | (unsigned long long)code;
+    atomicMin(err, w);
+}
+
+__device__ double fresnel_real_d(double c, double ni, double nt)
+{
+    if (ni == nt) return 0.0;
+    const double m = ni / nt;
+    const double s2t = m * m * (1.0 - c * c);
+    if (s2t >= 1.0) return 1.0;
+    const double ct = sqrt(1.0 - s2t);
+    const double rs = (m * c - ct) / (m * c + ct);
+    const double rp = (c - m * ct) / (c + m * ct);
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+__global__ void pack_items(PackArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_items) return;
+    const int L = a.n_layers[i];
+    if (L < 1 || L > a.max_layers) { report(a.err, i, 0, kErrNLayers); return; }
+    const size_t o = (size_t)i * a.max_layers;
+    const float nu = a.n_upper[i], nl = a.n_lower[i], kl = a.k_lower[i], mu0 = a.mu0[i];
+    bool bad = false;
+    if (!finite_(nu) || nu < 1.0f) { report(a.err, i, 0, kErrNUpper); bad = true; }
+    if (!finite_(nl) || !(nl > 0.0f)) { report(a.err, i, 0, kErrNLower); bad = true; }
+    if (!finite_(kl) || kl < 0.0f) { report(a.err, i, 0, kErrKLower); bad = true; }
+    if (!finite_(mu0) || !(mu0 > 0.0f) || mu0 > 1.0f) { report(a.err, i, 0, kErrMu0); bad = true; }
+    for (int l = 0; l < L; ++l) {
+        const float s = a.mu_s[o + l], ab = a.mu_a[o + l], g = a.g[o + l];
+        const float n = a.n_layer[o + l], t = a.thickness[o + l];
+        if (!finite_(s) || s < 0.0f) { report(a.err, i, l, kErrMuS); bad = true; }
+        if (!finite_(ab) || ab < 0.0f) { report(a.err, i, l, kErrMuA); bad = true; }
+        if (!finite_(g) || g < -1.0f || g > 1.0f) { report(a.err, i, l, kErrG); bad = true; }
+        if (!finite_(n) || n < 1.0f) { report(a.err, i, l, kErrNLayer); bad = true; }
+        if (!finite_(t) || !(t > 0.0f)) { report(a.err, i, l, kErrThickness); bad = true; }
+    }
+    if (bad) return;
+
+    float4* rec = a.table + (size_t)i * rec_f4(a.max_layers);
+    // entry: Fresnel from the upper medium into layer 1, refracted cosine
+    const double n1 = a.n_layer[o];
+    const double R0 = fresnel_real_d((double)mu0, (double)nu, n1);
+    const double r = (double)nu / n1;
+    const double s2t = r * r * (1.0 - (double)mu0 * mu0);
+    const double uz0 = s2t < 1.0 ? sqrt(1.0 - s2t) : 0.0;
+    rec[0] = make_float4((float)R0, (float)uz0, nl, kl);
+    const uint64_t N = a.photons[i];
+    rec[1] = make_float4(__uint_as_float((uint32_t)N), __uint_as_float((uint32_t)(N >> 32)),
+                         __int_as_float(L), __int_as_float(i));
+    for (int l = 0; l < L; ++l) {
+        const double s = a.mu_s[o + l], ab = a.mu_a[o + l], g = a.g[o + l];
+        const double n = a.n_layer[o + l], t = a.thickness[o + l];
+        const double mut = s + ab;
+        const float alb = mut > 0.0 ? (float)(s / mut) : 0.0f;
+        const float inv = mut > 0.0 ? (float)(1.0 / mut) : 0.0f;
+        float hG, hh, q1, q2;
+        bool mirror;
+        hg_constants(g, hG, hh, q1, q2, mirror);
+        const double n_up = (l == 0) ? (double)nu : (double)a.n_layer[o + l - 1];
+        const double n_dn = (l == L - 1) ? (double)nl : (double)a.n_layer[o + l + 1];
+        uint32_t fl = 0;
+        if (l == 0) fl |= kExitUp;
+        if (l == L - 1) { fl |= kExitDn; if (kl > 0.0f) fl |= kComplexDn; }
+        if (n_up == n) fl |= kMatchUp;
+        if (n_dn == n && !(fl & kComplexDn)) fl |= kMatchDn;
+        if (mirror) fl |= kHgMirror;
+        float4* lr = rec + kHdrF4 + kLayerF4 * l;
+        lr[0] = make_float4((float)mut, alb, inv, (float)t);
+        lr[1] = make_float4(hG, hh, q1, q2);
+        lr[2] = make_float4((float)(n / n_up), (float)(n / n_dn), (float)n, __uint_as_float(fl));
+        lr[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+__global__ void reset_run(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
+                          int n_items)
+{
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t j = tid; j < (size_t)n_items * kNTally; j += stride) tallies[j] = 0ull;
+    for (size_t j = tid; j < (size_t)n_items; j += stride) cursors[j] = 0ull;
+    if (tid == 0) *cur_item = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// the persistent walk
+// ---------------------------------------------------------------------------
+// Each wave works on its own: it claims chunks of photons of one item from a
+// global queue (an item cursor plus a per-item photon cursor), stages the
+// item's record into one of kSlots LDS slots of its own, and fills idle lanes
+// with new photons from the chunk.  A lane keeps the parameters of its
+// current layer in registers and re-reads the LDS slot only when it launches
+// a photon or crosses into another layer.  Lanes that finish are refilled
+// once at least refill_min of them are idle, so a wave keeps walking while
+// the photons of an old chunk drain.  Outcomes are counted per slot in LDS
+// (a ballot/popcount per outcome when all finishing lanes share a slot) and
+// added to the item's uint64 tallies when a slot is recycled and at exit.
+constexpr int kSlots = 4;
+
+struct LaneLayer {
+    float mut, alb, inv_mut, thick;
+    float hG, hh, q1, q2;
+    float m_up, m_dn, n;
+    uint32_t flags;
+};
+
+__device__ __forceinline__ void load_layer(const float4* slot_rec, int l, LaneLayer& P)
+{
+    const float4* lr = slot_rec + kHdrF4 + kLayerF4 * l;
+    const float4 a = lr[0], b = lr[1], c = lr[2];
+    P.mut = a.x; P.alb = a.y; P.inv_mut = a.z; P.thick = a.w;
+    P.hG = b.x; P.hh = b.y; P.q1 = b.z; P.q2 = b.w;
+    P.m_up = c.x; P.m_dn = c.y; P.n = c.z; P.flags = __float_as_uint(c.w);
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_rank(uint64_t mask)
+{
+    // number of set bits of mask below this lane
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int kStepsPerCheck>
+__global__ void walk(WalkArgs a)
+{
+    extern __shared__ float4 smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int rf = a.rec_f4;
+    float4* tab = smem + (size_t)wv * kSlots * rf;                         // [kSlots][rf]
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(smem + (size_t)nwaves * kSlots * rf) +
+                              (size_t)wv * kSlots * kNTally;                 // [kSlots][6]
+    int* slot_item = reinterpret_cast<int*>(reinterpret_cast<unsigned long long*>(
+                         smem + (size_t)nwaves * kSlots * rf) + (size_t)nwaves * kSlots * kNTally) +
+                     wv * kSlots;                                            // [kSlots]
+
+    for (int j = lane; j < kSlots * kNTally; j += 64) cnt[j] = 0ull;
+    if (lane < kSlots) slot_item[lane] = -1;
+    wave_sync_lds();
+
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t max_steps = a.max_steps;
+
+    // lane state
+    bool alive = false;
+    int slot = 0, layer = 0;
+    uint32_t item = 0, p_lo = 0, p_hi = 0, k = 0;
+    float z = 0.f, uz = 1.f, s = 0.f;
+    LaneLayer P;
+    P.mut = P.alb = P.inv_mut = P.thick = P.hG = P.hh = P.q1 = P.q2 = P.m_up = P.m_dn = P.n = 0.f;
+    P.flags = 0u;
+
+    // wave-uniform source chunk
+    int src_slot = -1, src_item = -1;
+    uint64_t src_next = 0, src_end = 0;
+    bool queue_done = false;
+
+    for (;;) {
+        // ---------------- refill ----------------
+        uint64_t dead = ballot64(!alive);
+        while (dead != 0ull && (__popcll(dead) >= a.refill_min || dead == ~0ull)) {
+            if (src_next >= src_end) {
+                if (queue_done) break;
+                const int ns = (src_slot + 1) % kSlots;
+                if (ballot64(alive && slot == ns) != 0ull) break;   // slot still draining
+                // claim a chunk: lane 0 walks the item cursor
+                int c_item = -1;
+                unsigned long long c_start = 0ull, c_end = 0ull;
+                if (lane == 0) {
+                    for (;;) {
+                        const uint32_t it = __hip_atomic_load(a.cur_item, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (it >= (uint32_t)a.n_items) break;
+                        const float4 h1 = a.table[(size_t)it * rf + 1];
+                        const uint64_t N = (uint64_t)__float_as_uint(h1.x) |
+                                           ((uint64_t)__float_as_uint(h1.y) << 32);
+                        const unsigned long long st = atomicAdd(a.cursors + it, (unsigned long long)a.chunk);
+                        if (st < N) {
+                            c_item = (int)it;
+                            c_start = st;
+                            c_end = (st + (uint64_t)a.chunk < N) ? st + (uint64_t)a.chunk : N;
+                            break;
+                        }
+                        atomicCAS(a.cur_item, it, it + 1u);
+                    }
+                }
+                c_item = __builtin_amdgcn_readfirstlane(c_item);
+                c_start = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c_start >> 32)) << 32) |
+                          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)c_start);
+                c_end = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c_end >> 32)) << 32) |
+                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)c_end);
+                if (c_item < 0) { queue_done = true; break; }
+                if (c_item != src_item) {
+                    // recycle slot ns: flush its counts, stage the new item
+                    const int old = slot_item[ns];
+                    if (old >= 0 && lane < kNTally) {
+                        const unsigned long long v = cnt[ns * kNTally + lane];
+                        if (v) atomicAdd(a.tallies + (size_t)old * kNTally + lane, v);
+                    }
+                    wave_sync_lds();
+                    if (lane < kNTally) cnt[ns * kNTally + lane] = 0ull;
+                    for (int j = lane; j < rf; j += 64) tab[ns * rf + j] = a.table[(size_t)c_item * rf + j];
+                    if (lane == 0) slot_item[ns] = c_item;
+                    wave_sync_lds();
+                    src_slot = ns;
+                    src_item = c_item;
+                }
+                src_next = c_start;
+                src_end = c_end;
+            }
+            // hand photons of the source chunk to idle lanes
+            const uint64_t avail = src_end - src_next;
+            const int nd = __popcll(dead);
+            const int take = (uint64_t)nd < avail ? nd : (int)avail;
+            const int rank = lane_rank(dead);
+            const bool mine = !alive && rank < take;
+            bool spec = false;
+            if (mine) {
+                const uint64_t p = src_next + (uint64_t)rank;
+                const float4* sr = tab + src_slot * rf;
+                const float4 h0 = sr[0];
+                p_lo = (uint32_t)p; p_hi = (uint32_t)(p >> 32);
+                item = (uint32_t)src_item;
+                const uint4 x = philox4x32_10(p_lo, p_hi, 0u, item, k0, k1);
+                if (u24(x.y) < h0.x) {
+                    spec = true;                        // specular reflection
+                } else {
+                    alive = true;
+                    slot = src_slot;
+                    layer = 0;
+                    z = 0.f; uz = h0.y; s = 0.f; k = 0u;
+                    load_layer(sr, 0, P);
+                }
+            }
+            const uint64_t sm = ballot64(spec);
+            if (sm != 0ull && lane == 0)
+                atomicAdd(cnt + src_slot * kNTally + kRSpec, (unsigned long long)__popcll(sm));
+            src_next += (uint64_t)take;
+            dead = ballot64(!alive);
+        }
+        if (dead == ~0ull) break;   // queue exhausted and nothing in flight
+
+        // ---------------- walk ----------------
+        for (int it = 0; it < kStepsPerCheck; ++it) {
+            int term = -1;
+            if (alive) {
+                ++k;
+                if (k > max_steps) {
+                    k = max_steps;
+                    term = kCap;
+                } else {
+                    const uint4 x = philox4x32_10(p_lo, p_hi, k, item, k0, k1);
+                    const float U1 = u24(x.y);
+                    if (s == 0.f) s = -__logf(1.0f - u24(x.x));
+                    const float aa = fabsf(uz);
+                    bool interact;
+                    if (aa == 0.f) {
+                        interact = P.mut > 0.f;
+                        if (!interact) term = kCap;      // parallel in a clear layer
+                    } else {
+                        const bool down = uz > 0.f;
+                        const float dz = down ? P.thick - z : z;
+                        interact = !(P.mut * dz <= s * aa);
+                        if (!interact) {
+                            // reach the interface
+                            s = fmaxf(s - P.mut * dz / aa, 0.f);
+                            z = down ? P.thick : 0.f;
+                            const uint32_t fl = P.flags;
+                            const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);
+                            const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);
+                            float R = 0.f, ct = aa;
+                            if (down && (fl & kComplexDn)) {
+                                const float4 h0 = tab[slot * rf];
+                                R = fresnel_complex(aa, P.n, h0.z, h0.w);
+                            } else if (!matched) {
+                                const float m = down ? P.m_dn : P.m_up;
+                                const float s2t = m * m * (1.f - aa * aa);
+                                if (s2t >= 1.f) {
+                                    R = 1.f;
+                                } else {
+                                    ct = sqrtf(1.f - s2t);
+                                    R = fresnel_real(aa, ct, m);
+                                }
+                            }
+                            if (U1 < R) {
+                                uz = -uz;
+                            } else if (ex) {
+                                term = down ? kTrans : kRDiff;
+                            } else {
+                                layer += down ? 1 : -1;
+                                load_layer(tab + slot * rf, layer, P);
+                                uz = down ? ct : -ct;
+                                z = down ? 0.f : P.thick;
+                            }
+                        } else {
+                            z = fmaf(uz * s, P.inv_mut, z);
+                            s = 0.f;
+                        }
+                    }
+                    if (interact) {
+                        if (U1 < P.alb) {
+                            const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,
+                                                   u24(x.z));
+                            const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
+                            const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
+                            uz = fminf(fmaxf(fmaf(uz, c, sqrtf(st2) * cp), -1.f), 1.f);
+                        } else {
+                            term = kAbs;
+                        }
+                    }
+                }
+            }
+            // ---- tallies of photons that finished in this step ----
+            const uint64_t tm = ballot64(term >= 0);
+            if (tm != 0ull) {
+                if (term >= 0) {
+                    alive = false;
+                    atomicAdd(cnt + slot * kNTally + kSteps, (unsigned long long)k);
+                }
+                const int lead = __builtin_ctzll(tm);
+                const int s0 = __shfl(slot, lead);
+                if (ballot64(term >= 0 && slot != s0) == 0ull) {
+                    // every finishing lane shares slot s0: one popcount per outcome
+                    unsigned long long* c0 = cnt + s0 * kNTally;
+#pragma unroll
+                    for (int o = kRDiff; o <= kCap; ++o) {
+                        const uint64_t bo = ballot64(term == o);
+                        if (bo != 0ull && lane == 0) atomicAdd(c0 + o, (unsigned long long)__popcll(bo));
+                    }
+                } else if (term >= 0) {
+                    atomicAdd(cnt + slot * kNTally + term, 1ull);
+                }
+                if (__popcll(ballot64(!alive)) >= a.refill_min) break;
+            }
+        }
+    }
+
+    // exit: flush every slot of this wave
+    wave_sync_lds();
+    for (int sl = 0; sl < kSlots; ++sl) {
+        const int it = slot_item[sl];
+        if (it >= 0 && lane < kNTally) {
+            const unsigned long long v = cnt[sl * kNTally + lane];
+            if (v) atomicAdd(a.tallies + (size_t)it * kNTally + lane, v);
+        }
+    }
+}
+
+size_t walk_lds_bytes(int block_size, int max_layers)
+{
+    const int nw = block_size / 64;
+    return (size_t)nw * kSlots * rec_f4(max_layers) * sizeof(float4) +
+           (size_t)nw * kSlots * kNTally * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int);
+}
+
+hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st)
+{
+    const size_t lds = walk_lds_bytes(block, a.max_layers);
+    hipLaunchKernelGGL(walk<4>, dim3(grid), dim3(block), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs& a, hipStream_t st)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const int b = 256;
+    hipLaunchKernelGGL(pack_items, dim3((a.n_items + b - 1) / b), dim3(b), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
+                        int n_items, hipStream_t st)
+{
+    int blocks = (int)(((size_t)n_items * kNTally + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(reset_run, dim3(blocks), dim3(256), 0, st, tallies, cursors, cur_item, n_items);
+    return hipGetLastError();
+}
+
+__global__ void fill_u64(unsigned long long* p, unsigned long long v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// test hooks
+// ---------------------------------------------------------------------------
+__global__ void philox_words_k(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
+                               uint64_t seed, uint32_t* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint64_t p = photon[j];
+    const uint4 x = philox4x32_10((uint32_t)p, (uint32_t)(p >> 32), step[j], stream[j], (uint32_t)seed,
+                                  (uint32_t)(seed >> 32));
+    out[4 * j + 0] = x.x; out[4 * j + 1] = x.y; out[4 * j + 2] = x.z; out[4 * j + 3] = x.w;
+}
+
+hipError_t launch_philox_words(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
+                               uint64_t seed, uint32_t* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_words_k, dim3((n + 255) / 256), dim3(256), 0, st, n, photon, step, stream, seed, out);
+    return hipGetLastError();
+}
+
+// Fresnel exactly as the walk evaluates it: real interfaces by ratio
+// m = ni/nt (total internal reflection -> 1), complex lower media by the
+// impedance form.
+__global__ void eval_fresnel_k(int n, const float* c, const float* ni, const float* nt, const float* kt,
+                               float* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float aa = c[j];
+    float R;
+    if (kt[j] > 0.f) {
+        R = fresnel_complex(aa, ni[j], nt[j], kt[j]);
+    } else if (ni[j] == nt[j]) {
+        R = 0.f;
+    } else {
+        const float m = ni[j] / nt[j];
+        const float s2t = m * m * (1.f - aa * aa);
+        R = s2t >= 1.f ? 1.f : fresnel_real(aa, sqrtf(1.f - s2t), m);
+    }
+    out[j] = R;
+}
+
+hipError_t launch_eval_fresnel(int n, const float* c, const float* ni, const float* nt, const float* kt,
+                               float* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_fresnel_k, dim3((n + 255) / 256), dim3(256), 0, st, n, c, ni, nt, kt, out);
+    return hipGetLastError();
+}
+
+__global__ void eval_hg_k(int n, const float* g, const float* u01, float* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float G, h, q1, q2;
+    bool mirror;
+    hg_constants((double)g[j], G, h, q1, q2, mirror);
+    out[j] = hg_cos(G, h, q1, q2, mirror, u01[j]);
+}
+
+hipError_t launch_eval_hg(int n, const float* g, const float* u01, float* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_hg_k, dim3((n + 255) / 256), dim3(256), 0, st, n, g, u01, out);
+    return hipGetLastError();
+}
+
+}  // namespace fos

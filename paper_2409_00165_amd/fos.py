@@ -1,0 +1,273 @@
+"""Python binding of libfos_mc (ctypes; argument marshalling only).
+
+Every function has the name of the C entry point it wraps (include/fos_mc.h)
+and takes torch tensors that already live on the context's GPU; PyTorch is
+used only for device memory and streams.  All compute happens in the HIP
+library: if ``libfos_mc.so`` is missing this module raises on first use --
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_float, c_int, c_int32, c_uint32, c_uint64, c_void_p
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfos_mc.so")
+
+FOS_MAX_LAYERS = 8
+N_TALLY = 6
+TALLY_NAMES = ("r_spec", "r_diff", "absorbed", "transmitted", "capped", "steps")
+STATUS = {0: "FOS_OK", 1: "FOS_E_INVALID_ARG", 2: "FOS_E_UNSUPPORTED", 3: "FOS_E_DEVICE",
+          4: "FOS_E_OUT_OF_MEMORY", 5: "FOS_E_INTERNAL", 6: "FOS_E_NOT_PREPARED"}
+
+
+class FosError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = STATUS.get(status, str(status))
+        super().__init__(f"{self.status_name}: {message}")
+
+
+class fos_mc_problem(Structure):
+    _fields_ = [("n_items", c_int32), ("max_layers", c_int32), ("n_layers", c_void_p),
+                ("mu_s", c_void_p), ("mu_a", c_void_p), ("g", c_void_p), ("n_layer", c_void_p),
+                ("thickness", c_void_p), ("n_upper", c_void_p), ("n_lower", c_void_p),
+                ("k_lower", c_void_p), ("mu0", c_void_p), ("photons", c_void_p)]
+
+
+class fos_mc_launch(Structure):
+    _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
+                ("blocks_per_cu", c_int32), ("max_steps", c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfos_mc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2409_00165_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fos_abi_version.restype = c_int
+        L.fos_status_string.restype = c_char_p
+        L.fos_status_string.argtypes = [c_int]
+        L.fos_create.argtypes = [c_int, POINTER(c_void_p)]
+        L.fos_create.restype = c_int
+        L.fos_destroy.argtypes = [c_void_p]
+        L.fos_destroy.restype = None
+        L.fos_last_error.argtypes = [c_void_p]
+        L.fos_last_error.restype = c_char_p
+        L.fos_mc_prepare.argtypes = [c_void_p, POINTER(fos_mc_problem), c_void_p]
+        L.fos_mc_prepare.restype = c_int
+        L.fos_mc_execute.argtypes = [c_void_p, c_uint64, POINTER(fos_mc_launch), c_void_p, c_void_p]
+        L.fos_mc_execute.restype = c_int
+        L.fos_mc_run.argtypes = [c_void_p, POINTER(fos_mc_problem), c_uint64, POINTER(fos_mc_launch),
+                                 c_void_p, c_void_p]
+        L.fos_mc_run.restype = c_int
+        L.fos_mc_prepared_items.argtypes = [c_void_p]
+        L.fos_mc_prepared_items.restype = c_int32
+        L.fos_mc_get_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
+        L.fos_mc_get_launch.restype = c_int
+        L.fos_mc_set_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
+        L.fos_mc_set_launch.restype = c_int
+        L.fos_philox_words.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p,
+                                       c_void_p]
+        L.fos_philox_words.restype = c_int
+        L.fos_eval_fresnel.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p]
+        L.fos_eval_fresnel.restype = c_int
+        L.fos_eval_hg.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fos_eval_hg.restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status: int):
+    if status != 0:
+        msg = fos_last_error(ctx) if ctx else ""
+        raise FosError(status, msg)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype=None, n=None):
+    """Device pointer of a contiguous torch tensor (checked)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libfos_mc takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def fos_abi_version() -> int:
+    return lib().fos_abi_version()
+
+
+def fos_status_string(s: int) -> str:
+    return lib().fos_status_string(s).decode()
+
+
+def fos_create(hip_device: int = 0):
+    h = c_void_p()
+    st = lib().fos_create(hip_device, ctypes.byref(h))
+    if st != 0:
+        raise FosError(st, f"fos_create(device={hip_device}) failed")
+    return h
+
+
+def fos_destroy(ctx) -> None:
+    if ctx:
+        lib().fos_destroy(ctx)
+
+
+def fos_last_error(ctx) -> str:
+    return lib().fos_last_error(ctx).decode()
+
+
+class MCProblem:
+    """Device tensors of one fos_mc_problem (kept alive with the struct)."""
+
+    def __init__(self, n_layers, mu_s, mu_a, g, n_layer, thickness, n_upper, n_lower, k_lower, mu0,
+                 photons):
+        import torch
+        self.tensors = dict(n_layers=n_layers, mu_s=mu_s, mu_a=mu_a, g=g, n_layer=n_layer,
+                            thickness=thickness, n_upper=n_upper, n_lower=n_lower, k_lower=k_lower,
+                            mu0=mu0, photons=photons)
+        I = n_layers.numel()
+        L = mu_s.numel() // max(I, 1) if I else (mu_s.shape[-1] if mu_s.dim() == 2 else 1)
+        self.n_items, self.max_layers = I, L
+        s = fos_mc_problem()
+        s.n_items, s.max_layers = I, L
+        s.n_layers = _ptr(n_layers, torch.int32, I)
+        for k in ("mu_s", "mu_a", "g", "n_layer", "thickness"):
+            setattr(s, k, _ptr(self.tensors[k], torch.float32, I * L))
+        for k in ("n_upper", "n_lower", "k_lower", "mu0"):
+            setattr(s, k, _ptr(self.tensors[k], torch.float32, I))
+        s.photons = _ptr(photons, torch.uint64 if hasattr(torch, "uint64") else torch.int64, I)
+        self.struct = s
+
+    @classmethod
+    def from_numpy(cls, device, n_layers, mu_s, mu_a, g, n_layer, thickness, n_upper, n_lower, k_lower,
+                   mu0, photons):
+        import numpy as np
+        import torch
+
+        def f32(x):
+            return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(device)
+
+        I = len(n_layers)
+        L = int(np.asarray(mu_s).reshape(I, -1).shape[1]) if I else 1
+        ph = torch.from_numpy(np.ascontiguousarray(photons, dtype=np.int64)).to(device)
+        if hasattr(torch, "uint64"):
+            ph = ph.view(torch.uint64)
+        return cls(torch.from_numpy(np.ascontiguousarray(n_layers, dtype=np.int32)).to(device),
+                   *[f32(np.asarray(a).reshape(I, L)) for a in (mu_s, mu_a, g, n_layer, thickness)],
+                   *[f32(a) for a in (n_upper, n_lower, k_lower, mu0)], ph)
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, fos_mc_launch):
+        return ctypes.byref(launch)
+    L = fos_mc_launch()
+    for k, v in dict(launch).items():
+        setattr(L, k, int(v))
+    return ctypes.byref(L)
+
+
+def fos_mc_prepare(ctx, problem: MCProblem, stream=None) -> None:
+    _check(ctx, lib().fos_mc_prepare(ctx, ctypes.byref(problem.struct), _stream(stream)))
+
+
+def fos_mc_execute(ctx, seed: int, tallies, launch=None, stream=None) -> None:
+    import torch
+    n = fos_mc_prepared_items(ctx)
+    _check(ctx, lib().fos_mc_execute(ctx, c_uint64(seed), _launch(launch),
+                                     _ptr(tallies, None, n * N_TALLY) if n else _ptr(tallies),
+                                     _stream(stream)))
+
+
+def fos_mc_run(ctx, problem: MCProblem, seed: int, tallies, launch=None, stream=None) -> None:
+    _ptr(tallies, None, problem.n_items * N_TALLY)
+    _check(ctx, lib().fos_mc_run(ctx, ctypes.byref(problem.struct), c_uint64(seed), _launch(launch),
+                                 _ptr(tallies), _stream(stream)))
+
+
+def fos_mc_prepared_items(ctx) -> int:
+    return lib().fos_mc_prepared_items(ctx)
+
+
+def fos_mc_get_launch(ctx) -> fos_mc_launch:
+    L = fos_mc_launch()
+    _check(ctx, lib().fos_mc_get_launch(ctx, ctypes.byref(L)))
+    return L
+
+
+def fos_mc_set_launch(ctx, launch) -> None:
+    _check(ctx, lib().fos_mc_set_launch(ctx, _launch(launch)))
+
+
+def fos_philox_words(ctx, photon, step, stream_ids, seed: int, out, stream=None) -> None:
+    n = photon.numel()
+    _check(ctx, lib().fos_philox_words(ctx, n, _ptr(photon), _ptr(step), _ptr(stream_ids), c_uint64(seed),
+                                       _ptr(out, None, 4 * n), _stream(stream)))
+
+
+def fos_eval_fresnel(ctx, c, ni, nt, kt, out, stream=None) -> None:
+    n = c.numel()
+    _check(ctx, lib().fos_eval_fresnel(ctx, n, _ptr(c), _ptr(ni), _ptr(nt), _ptr(kt), _ptr(out),
+                                       _stream(stream)))
+
+
+def fos_eval_hg(ctx, g, u01, out, stream=None) -> None:
+    n = g.numel()
+    _check(ctx, lib().fos_eval_hg(ctx, n, _ptr(g), _ptr(u01), _ptr(out), _stream(stream)))
+
+
+class Context:
+    """RAII wrapper: ``with Context(0) as ctx: fos_mc_run(ctx.handle, ...)``."""
+
+    def __init__(self, device: int = 0):
+        self.handle = fos_create(device)
+
+    def close(self):
+        if self.handle:
+            fos_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

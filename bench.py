@@ -1,0 +1,238 @@
+"""Benchmark: plain GPU Monte Carlo photon transport on one MI355X.
+
+Workload (the two-species paint slab): 500 log-spaced wavelengths
+0.3-16 um, one 500 um slab of matrix 1.5 + 1e-4 i with species A (f = 0.08)
+and B (f = 0.05), log-normal radii (median 0.25 um, sigma_ln 0.3, 20 bins),
+air on both sides, normal incidence, 1e6 photons per wavelength.  Inputs are
+synthetic (analytic material indices); the effective mu_s, mu_a, g of every
+wavelength are computed on the GPU by fos_optics_run before timing.
+
+One step = one pass of the transport hot path over the batch: fos_mc_prepare
+(validation + packing of the item table) and fos_mc_execute (the persistent
+walk), i.e. 5e8 photons.  The walk kernel's duration is taken with HIP
+events on the stream it runs on, inside the timed region.
+
+Prints one JSON line.  The CPU baseline is the FP64 oracle on a bounded
+sample of the same workload (every 10th wavelength, fewer photons).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one photon-step (a scattering step) in full-rate VALU
+# lane-op slots: the Philox4x32-10 block (20 32x32->64 multiplies at a
+# quarter of the full rate = 80 slots, 20 three-input xors = 20), four 24-bit
+# uniforms (12), the free path (log + 6), geometry and the move (11), the
+# albedo test (1), the Henyey-Greenstein sample (rcp + 10) and the direction
+# update (sqrt + cos + 7); transcendentals count 4 slots each.
+STEP_SLOTS = 160.0
+# gfx950 FP32 vector peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes;
+# one full-rate VALU lane-op slot per FMA lane per cycle.
+VALU_PEAK = 157.3e12 / 2.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_two_species_500_traffic.txt")
+KERNEL_SOURCES = ["paper_2409_00165_amd/csrc/mc_kernels.hip", "paper_2409_00165_amd/csrc/fos_device.hpp"]
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel_hash", "").strip() != kernel_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def gpu_problem(ctx, wl, device="cuda"):
+    """Optics on the GPU, then the transport problem as device tensors."""
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    req = W.optics_request(wl)
+    op = fos.OpticsProblem.from_request(req, device)
+    C = op.n_cells
+    mus = torch.zeros(C, dtype=torch.float32, device=device)
+    mua = torch.zeros(C, dtype=torch.float32, device=device)
+    g = torch.zeros(C, dtype=torch.float32, device=device)
+    fos.fos_optics_run(ctx, op, mus, mua, g)
+    geo = W.item_geometry(wl)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    ph = t(geo["photons"].astype(np.int64), np.int64)
+    if hasattr(torch, "uint64"):
+        ph = ph.view(torch.uint64)
+    prob = fos.MCProblem(t(geo["n_layers"], np.int32), mus, mua, g, t(geo["n_layer"], np.float32).reshape(-1),
+                         t(geo["thickness"], np.float32).reshape(-1), t(geo["n_upper"], np.float32),
+                         t(geo["n_lower"], np.float32), t(geo["k_lower"], np.float32), t(geo["mu0"], np.float32),
+                         ph)
+    return prob, (mus, mua, g)
+
+
+def cpu_baseline(wl, optics_host, seconds_target: float):
+    """FP64 oracle on every 10th wavelength; photons sized for ~target s."""
+    import oracle
+    from paper_2409_00165_amd import workloads as W
+    geo = W.item_geometry(wl)
+    idx = np.arange(0, wl.n_items, 10)
+    mus, mua, g = (np.asarray(a, np.float64).reshape(wl.n_items, -1)[idx] for a in optics_host)
+    f = lambda k: np.asarray(geo[k], np.float64)[idx]
+    threads = oracle.default_threads()
+
+    def run(n):
+        t0 = time.perf_counter()
+        o = oracle.walk_batch(geo["n_layers"][idx], mus, mua, g, f("n_layer"), f("thickness"), f("n_upper"),
+                              f("n_lower"), f("k_lower"), f("mu0"), np.full(len(idx), n, np.uint64),
+                              seed=0x0C9B, n_threads=threads)
+        return o, time.perf_counter() - t0
+
+    o, dt = run(2000)                       # calibration
+    rate = max(o[:, 5].sum() / max(dt, 1e-9), 1.0)
+    steps_per_photon = o[:, 5].sum() / (2000 * len(idx))
+    n = int(max(2000, min(1_000_000, seconds_target * rate / (steps_per_photon * len(idx)))))
+    o, dt = run(n)
+    steps = float(o[:, 5].sum())
+    return {"value": steps / dt, "unit": "photon-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of {wl.n_items} wavelengths (every 10th) x {n} photons, FP64, "
+                      f"{dt:.1f} s, {steps:.3e} photon-steps",
+            "cpu": _cpu_model(), "photons_per_s": len(idx) * n / dt}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=0x5EED)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (HBM counter calibration under rocprofv3)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the transport shards by items across GPUs with one tally gather, not built here)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    wl = W.two_species_500(photons=args.photons)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    launch = json.loads(args.launch) if args.launch else None
+    prob, optics = gpu_problem(h, wl)
+    I = prob.n_items
+    print(f"[bench] optics and problem ready: {I} items", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    tallies = [torch.zeros(I * fos.N_TALLY, dtype=torch.int64, device=dev) for _ in range(args.steps)]
+    warm = torch.zeros(I * fos.N_TALLY, dtype=torch.int64, device=dev)
+    for w in range(args.warmup):
+        fos.fos_mc_run(h, prob, args.seed + 1000 + w, warm, launch=launch)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        fos.fos_mc_prepare(h, prob)
+        ev[k][0].record(stream)
+        fos.fos_mc_execute(h, args.seed + k, tallies[k], launch=launch)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    tal = np.stack([t.cpu().numpy().reshape(I, fos.N_TALLY) for t in tallies])
+    steps_total = float(tal[:, :, 5].sum())
+    photons_total = float(tal[:, :, :5].sum())
+    assert photons_total == float(args.steps) * I * args.photons, "photon conservation failed"
+    walk_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    walk_s = float(walk_ms.mean()) / 1e3
+    steps_per_launch = steps_total / args.steps
+    achieved = STEP_SLOTS * steps_per_launch / walk_s
+    L = fos.fos_mc_get_launch(h).as_dict()
+    if launch:
+        L.update(launch)
+
+    rec = {
+        "metric": "photon-steps/s (plain GPU Monte Carlo, 500-wavelength two-species slab)",
+        "value": steps_total / elapsed,
+        "unit": "photon-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (analytic material indices; optics computed on the GPU)",
+        "config": {"workload": "two_species_500: 500 wavelengths 0.3-16 um, 500 um slab, species A f=0.08 + "
+                               "B f=0.05, log-normal r_med 0.25 um sigma_ln 0.3 x 20 bins, 1e6 photons/wavelength",
+                   "items": I, "photons_per_item": args.photons, "launch": L},
+        "photons_per_s": photons_total / elapsed,
+        "spectra_per_s": args.steps / elapsed,
+        "mean_steps_per_photon": steps_total / photons_total,
+        "walk_kernel_ms": float(walk_ms.mean()),
+        "walk_kernel_ms_all": [round(float(x), 3) for x in walk_ms],
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tslot/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
+                     "work_per_step_slots": STEP_SLOTS, "steps_per_launch": steps_per_launch,
+                     "kernel": "fos::walk", "kernel_hash": kernel_hash()},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        host = [o.cpu().numpy() for o in optics]
+        rec["cpu_baseline"] = cpu_baseline(wl, host, args.cpu_seconds)
+        rec["gpu_over_cpu"] = rec["value"] / rec["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -156,6 +156,45 @@ fos_status fos_mc_get_launch(const fos_ctx* ctx, fos_mc_launch* out);
 /* Set the context's launch defaults; fields equal to 0 keep their value. */
 fos_status fos_mc_set_launch(fos_ctx* ctx, const fos_mc_launch* launch);
 
+/* ------------------------------------------------------------------------- */
+/* Effective optics (Methodology, Scattering properties)                      */
+/* ------------------------------------------------------------------------- */
+
+/* Layer cells and their particle populations.  A cell is one (layer,
+ * wavelength) pair: vacuum wavelength lam, matrix index n_m + i k_m, and the
+ * particle entries offsets[c] .. offsets[c+1]-1 of the CSR arrays (one entry
+ * per particle size of each species: index n_p + i k_p, radius r, volume
+ * fraction f as a fraction, not a percentage).  All pointers DEVICE, double.
+ * Valid values: lam > 0, n_m > 0, k_m >= 0, n_p > 0, k_p >= 0, r > 0,
+ * f >= 0, offsets non-decreasing from offsets[0] = 0. */
+typedef struct {
+    int32_t n_cells;
+    const double* lam;        /* [n_cells] micrometres */
+    const double* n_m;        /* [n_cells] */
+    const double* k_m;        /* [n_cells] */
+    const int64_t* offsets;   /* [n_cells + 1] */
+    const double* n_p;        /* [offsets[n_cells]] */
+    const double* k_p;
+    const double* r;          /* micrometres */
+    const double* f;
+} fos_optics_problem;
+
+/* Effective mu_s, mu_a (1/micrometre) and g of every cell: Lorenz-Mie
+ * coefficients of each sphere in the absorbing host, eqs. (1)-(5), in the
+ * logarithmic-derivative form (the printed closed forms (6)-(9) are not
+ * used); efficiencies eqs. (10)-(12) with alpha = 4 pi r k_m / lambda;
+ * asymmetry eq. (15); the volume-fraction sums eqs. (13), (14), (16);
+ * negative sums set to zero; the dependent-scattering factor eqs. (17)-(19)
+ * when the cell's total volume fraction exceeds 0.08; matrix absorption
+ * eq. (20).  Outputs (DEVICE, any may be NULL): mu_s, mu_a, g float
+ * [n_cells] (cell c of a stack of max_layers layers laid out item-major is
+ * exactly the per-layer problem array element of fos_mc_problem), and
+ * out_f64 double [n_cells * 3] = (mu_s, mu_a, g).  Validates on the device
+ * and synchronises `hip_stream` for the verdict and the series length;
+ * FOS_E_INVALID_ARG names the first bad cell. */
+fos_status fos_optics_run(fos_ctx* ctx, const fos_optics_problem* problem, float* mu_s, float* mu_a,
+                          float* g, double* out_f64, void* hip_stream);
+
 /* Raw Philox4x32-10 words for testing the generator: out[4*j + w] =
  * word w of counter (p lo, p hi, step, stream) with p = photon[j],
  * key (seed lo, seed hi).  photon, step, stream DEVICE [n]; out DEVICE

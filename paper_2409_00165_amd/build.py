@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfos_mc.so")
 
-SOURCES = ["mc_kernels.hip", "runtime.hip"]
+SOURCES = ["mc_kernels.hip", "optics_kernels.hip", "runtime.hip"]
 HEADERS = ["fos_device.hpp", "fos_kernels.hpp"]
 
 # Packed FP32 VALU forms are kept out of the generated code.

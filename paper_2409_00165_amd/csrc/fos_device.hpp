@@ -47,8 +47,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -62,6 +63,13 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 // uniform in [0,1) from the top 24 bits of a word (exact in FP32)
 __device__ __forceinline__ float u24(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
 
+// Hardware approximations (about 1 ulp) used on the walk's hot path; their
+// error is far below the binomial noise of any tally.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// -ln(xi) for xi in [2^-24, 1] via the base-2 logarithm instruction
+__device__ __forceinline__ float neg_ln(float xi) { return -0.693147180559945309f * __builtin_amdgcn_logf(xi); }
+
 // ---------------------------------------------------------------------------
 // Fresnel reflectance, unpolarised.
 // Real interface, m = n_i / n_t, c = |cos theta_i|, ct = cos theta_t:
@@ -73,7 +81,7 @@ __device__ __forceinline__ float fresnel_real(float c, float ct, float m)
     const float a2 = c - m * ct, d2 = c + m * ct;
     const float num = a1 * a1 * (d2 * d2) + a2 * a2 * (d1 * d1);
     const float den = (d1 * d1) * (d2 * d2);
-    return 0.5f * num / den;
+    return 0.5f * num * fast_rcp(den);
 }
 
 // Absorbing lower medium N = n + i k seen from real index ni at cosine c:
@@ -84,21 +92,21 @@ __device__ __forceinline__ float fresnel_complex(float c, float ni, float n, flo
     const float A2 = n * n - k * k;         // Re N^2
     const float B = 2.0f * n * k;           // Im N^2 >= 0
     const float A = A2 - ni * ni * (1.0f - c * c);
-    const float mod = sqrtf(A * A + B * B);
+    const float mod = fast_sqrt(A * A + B * B);
     float qr, qi;
     if (A >= 0.0f) {
-        qr = sqrtf(0.5f * (mod + A));
-        qi = (qr > 0.0f) ? 0.5f * B / qr : 0.0f;
+        qr = fast_sqrt(0.5f * (mod + A));
+        qi = (qr > 0.0f) ? 0.5f * B * fast_rcp(qr) : 0.0f;
     } else {
-        qi = sqrtf(0.5f * (mod - A));
-        qr = (qi > 0.0f) ? 0.5f * B / qi : 0.0f;
+        qi = fast_sqrt(0.5f * (mod - A));
+        qr = (qi > 0.0f) ? 0.5f * B * fast_rcp(qi) : 0.0f;
     }
     const float nc = ni * c;
-    const float rs2 = ((nc - qr) * (nc - qr) + qi * qi) / ((nc + qr) * (nc + qr) + qi * qi);
+    const float rs2 = ((nc - qr) * (nc - qr) + qi * qi) * fast_rcp((nc + qr) * (nc + qr) + qi * qi);
     const float pr = A2 * c, pi = B * c;
     const float sr = ni * qr, si = ni * qi;
-    const float rp2 = ((pr - sr) * (pr - sr) + (pi - si) * (pi - si)) /
-                      ((pr + sr) * (pr + sr) + (pi + si) * (pi + si));
+    const float rp2 = ((pr - sr) * (pr - sr) + (pi - si) * (pi - si)) *
+                      fast_rcp((pr + sr) * (pr + sr) + (pi + si) * (pi + si));
     return fminf(0.5f * (rs2 + rp2), 1.0f);
 }
 
@@ -119,7 +127,7 @@ __device__ __forceinline__ float hg_cos(float G, float h, float q1, float q2, bo
     const float e = 2.0f * (mirror ? 1.0f - U : U);
     const float t = fmaf(G, e, h);
     const float num = fmaf(fmaf(q2, e, q1), e, -h * h);
-    float c = num / (t * t);
+    float c = num * fast_rcp(t * t);
     c = mirror ? -c : c;
     return fminf(fmaxf(c, -1.0f), 1.0f);
 }

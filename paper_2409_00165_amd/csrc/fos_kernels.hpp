@@ -43,6 +43,37 @@ struct WalkArgs {
     int refill_min;
 };
 
+enum OptErrCode : int {
+    kOptErrLambda = 1,
+    kOptErrNm = 2,
+    kOptErrKm = 3,
+    kOptErrOffsets = 4,
+    kOptErrNp = 5,
+    kOptErrKp = 6,
+    kOptErrRadius = 7,
+    kOptErrFraction = 8,
+};
+
+struct OpticsArgs {
+    int n_cells;
+    int64_t n_entries;
+    const double *lam, *n_m, *k_m;
+    const int64_t* offsets;
+    const double *n_p, *k_p, *r, *f;
+    int* cell_of;                 // [n_entries]
+    double* mie;                  // [n_entries * 3]: q_ext, q_sca, g
+    double2* scratch;             // [(nn_cap + 1) * mie threads]
+    unsigned int* nmax;           // largest series length + 1
+    int nn_cap;
+    unsigned long long* err;
+    float *out_mu_s, *out_mu_a, *out_g;
+    double* out_f64;              // [n_cells * 3] or NULL
+};
+
+hipError_t launch_optics_scan(const OpticsArgs& a, hipStream_t st);
+hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st);
+hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);
+
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
 hipError_t launch_reset(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
                         int n_items, hipStream_t st);

@@ -297,7 +297,7 @@ __global__ void walk(WalkArgs a)
                 } else {
                     const uint4 x = philox4x32_10(p_lo, p_hi, k, item, k0, k1);
                     const float U1 = u24(x.y);
-                    if (s == 0.f) s = -__logf(1.0f - u24(x.x));
+                    if (s == 0.f) s = neg_ln(1.0f - u24(x.x));
                     const float aa = fabsf(uz);
                     bool interact;
                     if (aa == 0.f) {
@@ -309,7 +309,7 @@ __global__ void walk(WalkArgs a)
                         interact = !(P.mut * dz <= s * aa);
                         if (!interact) {
                             // reach the interface
-                            s = fmaxf(s - P.mut * dz / aa, 0.f);
+                            s = fmaxf(s - P.mut * dz * fast_rcp(aa), 0.f);
                             z = down ? P.thick : 0.f;
                             const uint32_t fl = P.flags;
                             const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);
@@ -324,7 +324,7 @@ __global__ void walk(WalkArgs a)
                                 if (s2t >= 1.f) {
                                     R = 1.f;
                                 } else {
-                                    ct = sqrtf(1.f - s2t);
+                                    ct = fast_sqrt(1.f - s2t);
                                     R = fresnel_real(aa, ct, m);
                                 }
                             }
@@ -349,7 +349,7 @@ __global__ void walk(WalkArgs a)
                                                    u24(x.z));
                             const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
                             const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
-                            uz = fminf(fmaxf(fmaf(uz, c, sqrtf(st2) * cp), -1.f), 1.f);
+                            uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);
                         } else {
                             term = kAbs;
                         }
@@ -475,7 +475,7 @@ __global__ void eval_fresnel_k(int n, const float* c, const float* ni, const flo
     } else {
         const float m = ni[j] / nt[j];
         const float s2t = m * m * (1.f - aa * aa);
-        R = s2t >= 1.f ? 1.f : fresnel_real(aa, sqrtf(1.f - s2t), m);
+        R = s2t >= 1.f ? 1.f : fresnel_real(aa, fast_sqrt(1.f - s2t), m);
     }
     out[j] = R;
 }

@@ -28,6 +28,15 @@ struct fos_ctx {
     unsigned long long* err_dev = nullptr;   // device, 1 word
     unsigned long long* err_host = nullptr;  // pinned host, 1 word
     fos_mc_launch defaults{};
+    // optics scratch
+    int* cell_of = nullptr;
+    size_t cell_of_bytes = 0;
+    double* mie = nullptr;
+    size_t mie_bytes = 0;
+    double2* mie_scratch = nullptr;
+    size_t mie_scratch_bytes = 0;
+    unsigned int* nmax_dev = nullptr;        // device, 1 word
+    unsigned long long* aux_host = nullptr;  // pinned host, 4 words
 };
 
 namespace {
@@ -151,13 +160,15 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     c->device = hip_device;
     c->n_cu = prop.multiProcessorCount;
     c->defaults.block_size = 256;
-    c->defaults.refill_min = 16;
+    c->defaults.refill_min = 8;
     c->defaults.chunk = 4096;
     c->defaults.blocks_per_cu = 8;
     c->defaults.max_steps = 100000000ull;
     DeviceGuard g(hip_device);
     if (hipMalloc(reinterpret_cast<void**>(&c->cur_item), 256) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->err_dev), 256) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&c->nmax_dev), 256) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->aux_host), 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(unsigned long long)) != hipSuccess) {
         fos_destroy(c);
         return FOS_E_OUT_OF_MEMORY;
@@ -177,6 +188,11 @@ void fos_destroy(fos_ctx* c)
         if (c->cur_item) (void)hipFree(c->cur_item);
         if (c->err_dev) (void)hipFree(c->err_dev);
         if (c->err_host) (void)hipHostFree(c->err_host);
+        if (c->aux_host) (void)hipHostFree(c->aux_host);
+        if (c->nmax_dev) (void)hipFree(c->nmax_dev);
+        if (c->cell_of) (void)hipFree(c->cell_of);
+        if (c->mie) (void)hipFree(c->mie);
+        if (c->mie_scratch) (void)hipFree(c->mie_scratch);
     }
     delete c;
 }
@@ -295,6 +311,93 @@ fos_status fos_mc_run(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const 
     fos_status s = fos_mc_prepare(c, p, hip_stream);
     if (s != FOS_OK) return s;
     return fos_mc_execute(c, seed, launch, tallies, hip_stream);
+}
+
+static const char* optics_field_name(int code)
+{
+    switch (code) {
+    case fos::kOptErrLambda: return "lam (must be finite and > 0)";
+    case fos::kOptErrNm: return "n_m (must be finite and > 0)";
+    case fos::kOptErrKm: return "k_m (must be finite and >= 0)";
+    case fos::kOptErrOffsets: return "offsets (must be non-decreasing within [0, offsets[n_cells]])";
+    case fos::kOptErrNp: return "n_p (must be finite and > 0)";
+    case fos::kOptErrKp: return "k_p (must be finite and >= 0)";
+    case fos::kOptErrRadius: return "r (must be finite and > 0)";
+    case fos::kOptErrFraction: return "f (must be finite and >= 0)";
+    default: return "unknown field";
+    }
+}
+
+fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, float* mu_a, float* g,
+                          double* out_f64, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!p) return fail(c, FOS_E_INVALID_ARG, "problem is NULL");
+    if (p->n_cells < 0) return fail(c, FOS_E_INVALID_ARG, "n_cells must be >= 0");
+    if (p->n_cells == 0) return FOS_OK;
+    if (!p->lam || !p->n_m || !p->k_m || !p->offsets)
+        return fail(c, FOS_E_INVALID_ARG, "a cell array pointer is NULL");
+    DeviceGuard guard(c->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    // number of particle entries and offsets[0]
+    if ((e = hipMemcpyAsync(&c->aux_host[0], p->offsets + p->n_cells, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&c->aux_host[1], p->offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "optics offsets");
+    const int64_t P = (int64_t)c->aux_host[0];
+    if ((int64_t)c->aux_host[1] != 0 || P < 0)
+        return fail(c, FOS_E_INVALID_ARG, "offsets[0] must be 0 and offsets[n_cells] >= 0");
+    if (P > 0 && (!p->n_p || !p->k_p || !p->r || !p->f))
+        return fail(c, FOS_E_INVALID_ARG, "a particle array pointer is NULL");
+    if ((e = grow(c->cell_of, c->cell_of_bytes, (size_t)std::max<int64_t>(P, 1) * sizeof(int))) != hipSuccess)
+        return hip_fail(c, e, "optics scratch");
+    if ((e = grow(c->mie, c->mie_bytes, (size_t)std::max<int64_t>(P, 1) * 3 * sizeof(double))) != hipSuccess)
+        return hip_fail(c, e, "optics scratch");
+    fos::OpticsArgs a{};
+    a.n_cells = p->n_cells;
+    a.n_entries = P;
+    a.lam = p->lam; a.n_m = p->n_m; a.k_m = p->k_m; a.offsets = p->offsets;
+    a.n_p = p->n_p; a.k_p = p->k_p; a.r = p->r; a.f = p->f;
+    a.cell_of = c->cell_of;
+    a.mie = c->mie;
+    a.nmax = c->nmax_dev;
+    a.err = c->err_dev;
+    a.out_mu_s = mu_s; a.out_mu_a = mu_a; a.out_g = g; a.out_f64 = out_f64;
+    if ((e = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess ||
+        (e = fos::launch_fill_u64(reinterpret_cast<unsigned long long*>(c->nmax_dev), 0ull, 1, st)) != hipSuccess ||
+        (e = fos::launch_optics_scan(a, st)) != hipSuccess)
+        return hip_fail(c, e, "optics scan");
+    if ((e = hipMemcpyAsync(c->err_host, c->err_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&c->aux_host[2], c->nmax_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "optics verdict");
+    const unsigned long long w = *c->err_host;
+    if (w != ~0ull) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "cell %llu: invalid %s", w >> 8, optics_field_name((int)(w & 0xFF)));
+        return fail(c, FOS_E_INVALID_ARG, buf);
+    }
+    const int nn_cap = (int)(c->aux_host[2] & 0xFFFFFFFFull);
+    if (nn_cap > (1 << 20)) return fail(c, FOS_E_UNSUPPORTED, "Mie series longer than 2^20 terms");
+    const int block = 256;
+    int grid = c->n_cu * 4;
+    const int64_t need = (P + block - 1) / block;
+    if (need < grid) grid = (int)std::max<int64_t>(need, 1);
+    a.nn_cap = std::max(nn_cap, 1);
+    const size_t nthreads = (size_t)grid * block;
+    if ((e = grow(c->mie_scratch, c->mie_scratch_bytes, ((size_t)a.nn_cap + 1) * nthreads * sizeof(double2))) !=
+        hipSuccess)
+        return hip_fail(c, e, "Mie scratch");
+    a.scratch = c->mie_scratch;
+    if ((e = fos::launch_mie(a, grid, block, st)) != hipSuccess) return hip_fail(c, e, "Mie kernel");
+    if ((e = fos::launch_emt(a, st)) != hipSuccess) return hip_fail(c, e, "effective-medium kernel");
+    return FOS_OK;
 }
 
 fos_status fos_philox_words(fos_ctx* c, int32_t n, const uint64_t* photon, const uint32_t* step,

@@ -36,6 +36,12 @@ class fos_mc_problem(Structure):
                 ("k_lower", c_void_p), ("mu0", c_void_p), ("photons", c_void_p)]
 
 
+class fos_optics_problem(Structure):
+    _fields_ = [("n_cells", c_int32), ("lam", c_void_p), ("n_m", c_void_p), ("k_m", c_void_p),
+                ("offsets", c_void_p), ("n_p", c_void_p), ("k_p", c_void_p), ("r", c_void_p),
+                ("f", c_void_p)]
+
+
 class fos_mc_launch(Structure):
     _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
                 ("blocks_per_cu", c_int32), ("max_steps", c_uint64)]
@@ -77,6 +83,9 @@ def lib():
         L.fos_mc_get_launch.restype = c_int
         L.fos_mc_set_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
         L.fos_mc_set_launch.restype = c_int
+        L.fos_optics_run.argtypes = [c_void_p, POINTER(fos_optics_problem), c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p]
+        L.fos_optics_run.restype = c_int
         L.fos_philox_words.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p,
                                        c_void_p]
         L.fos_philox_words.restype = c_int
@@ -230,6 +239,42 @@ def fos_mc_get_launch(ctx) -> fos_mc_launch:
 
 def fos_mc_set_launch(ctx, launch) -> None:
     _check(ctx, lib().fos_mc_set_launch(ctx, _launch(launch)))
+
+
+class OpticsProblem:
+    """Device tensors of one fos_optics_problem (float64 cells, CSR particles)."""
+
+    def __init__(self, lam, n_m, k_m, offsets, n_p, k_p, r, f):
+        import torch
+        self.tensors = dict(lam=lam, n_m=n_m, k_m=k_m, offsets=offsets, n_p=n_p, k_p=k_p, r=r, f=f)
+        C = lam.numel()
+        P = n_p.numel()
+        s = fos_optics_problem()
+        s.n_cells = C
+        for k in ("lam", "n_m", "k_m"):
+            setattr(s, k, _ptr(self.tensors[k], torch.float64, C))
+        s.offsets = _ptr(offsets, torch.int64, C + 1)
+        for k in ("n_p", "k_p", "r", "f"):
+            setattr(s, k, _ptr(self.tensors[k], torch.float64, P) if P else None)
+        self.n_cells, self.n_entries, self.struct = C, P, s
+
+    @classmethod
+    def from_request(cls, req, device="cuda"):
+        """From a workloads.optics_request() dict of numpy arrays."""
+        import numpy as np
+        import torch
+        t = lambda k, dt=np.float64: torch.from_numpy(np.ascontiguousarray(req[k], dtype=dt)).to(device)
+        return cls(t("lam"), t("n_m"), t("k_m"), t("offsets", np.int64), t("n_p"), t("k_p"), t("r"), t("f"))
+
+
+def fos_optics_run(ctx, problem: OpticsProblem, mu_s=None, mu_a=None, g=None, out_f64=None,
+                   stream=None) -> None:
+    import torch
+    C = problem.n_cells
+    _check(ctx, lib().fos_optics_run(ctx, ctypes.byref(problem.struct),
+                                     _ptr(mu_s, torch.float32, C), _ptr(mu_a, torch.float32, C),
+                                     _ptr(g, torch.float32, C), _ptr(out_f64, torch.float64, 3 * C),
+                                     _stream(stream)))
 
 
 def fos_philox_words(ctx, photon, step, stream_ids, seed: int, out, stream=None) -> None:

@@ -1,0 +1,112 @@
+"""GPU effective-medium optics (Mie + eqs. (13)-(20)) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2409_00165_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2409_00165_amd import fos
+    c = fos.Context(0)
+    yield c.handle
+    c.close()
+
+
+def _gpu_optics(ctx, torch, req):
+    from paper_2409_00165_amd import fos
+    prob = fos.OpticsProblem.from_request(req)
+    C = prob.n_cells
+    o64 = torch.zeros(3 * C, dtype=torch.float64, device="cuda")
+    f32 = [torch.zeros(C, dtype=torch.float32, device="cuda") for _ in range(3)]
+    fos.fos_optics_run(ctx, prob, *f32, out_f64=o64)
+    torch.cuda.synchronize()
+    return o64.cpu().numpy().reshape(C, 3), np.stack([t.cpu().numpy() for t in f32], 1)
+
+
+def _geometric_scale(req):
+    """0.75 sum(f/r) per cell: the extinction of the cell's particles if every
+    efficiency were one, a floor for cells that barely scatter."""
+    off = np.asarray(req["offsets"])
+    w = 0.75 * np.asarray(req["f"]) / np.asarray(req["r"]) if len(req["r"]) else np.zeros(0)
+    c = np.concatenate([[0.0], np.cumsum(w)])
+    return c[off[1:]] - c[off[:-1]]
+
+
+def _compare(ref, got, label, rtol=1e-9, gtol=1e-8, floor=None):
+    """mu_s and mu_a to rtol of the cell's extinction mu_s + mu_a (mu_a is a
+    difference q_ext - q_sca of nearly equal series for weak absorbers), with
+    the particles' geometric extinction as a floor; g to gtol absolute where
+    scattering is not negligible (g of a vanishing scatterer is a ratio of
+    rounding noise)."""
+    ext = np.maximum(ref[:, 0] + ref[:, 1], 1e-300)
+    if floor is not None:
+        ext = np.maximum(ext, floor)
+    e_s = np.abs(got[:, 0] - ref[:, 0]) / ext
+    e_a = np.abs(got[:, 1] - ref[:, 1]) / ext
+    sig = ref[:, 0] > 1e-12 * ext
+    e_g = np.where(sig, np.abs(got[:, 2] - ref[:, 2]), 0.0)
+    print(label, "max err: mu_s/ext %.2e  mu_a/ext %.2e  g %.2e" % (e_s.max(), e_a.max(), e_g.max()), flush=True)
+    assert e_s.max() <= rtol and e_a.max() <= rtol, (np.argmax(e_s), np.argmax(e_a))
+    assert e_g.max() <= gtol, np.argmax(e_g)
+
+
+@pytest.mark.parametrize("name", ["single_slab_23", "two_species_500"])
+def test_workload_optics_match_oracle(ctx, torch, orc, name):
+    wl = getattr(W, name)()
+    req = W.optics_request(wl)
+    ref = orc.optics_batch(req)
+    got64, got32 = _gpu_optics(ctx, torch, req)
+    _compare(ref, got64, name, floor=_geometric_scale(req))
+    assert np.array_equal(got32, got64.astype(np.float32))
+
+
+def test_three_layer_designs_match_oracle(ctx, torch, orc):
+    wl = W.stacks_3layer(n_designs=12, n_lambda=100)
+    req = W.optics_request(wl)
+    _compare(orc.optics_batch(req), _gpu_optics(ctx, torch, req)[0], "stacks_3layer",
+             floor=_geometric_scale(req))
+
+
+def test_edge_cells(ctx, torch, orc):
+    # matrix only; index-matched sphere; tiny Rayleigh sphere; big sphere;
+    # strongly absorbing host; metal-like particle; crossing the 8 % threshold
+    cells = [
+        (0.5, 1.5, 1e-4, []),
+        (0.5, 1.5, 0.0, [(1.5, 0.0, 0.3, 0.05)]),
+        (2.0, 1.33, 0.0, [(1.5, 0.1, 0.002, 0.01)]),
+        (0.4, 1.0, 0.0, [(1.5, 0.01, 30.0, 0.2)]),
+        (1.0, 1.5, 0.05, [(2.4, 0.01, 0.5, 0.1)]),
+        (0.6, 1.0, 0.0, [(0.2, 3.0, 0.05, 0.02), (0.2, 3.0, 0.08, 0.02)]),
+        (0.7, 1.5, 1e-4, [(2.6, 1e-3, 0.2, 0.05), (1.45, 0.3, 0.4, 0.0300001)]),
+    ]
+    lam = np.array([c[0] for c in cells]); nm = np.array([c[1] for c in cells]); km = np.array([c[2] for c in cells])
+    counts = [len(c[3]) for c in cells]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    parts = [p for c in cells for p in c[3]]
+    req = dict(lam=lam, n_m=nm, k_m=km, offsets=off, n_p=np.array([p[0] for p in parts]),
+               k_p=np.array([p[1] for p in parts]), r=np.array([p[2] for p in parts]),
+               f=np.array([p[3] for p in parts]), cells=len(cells))
+    ref = orc.optics_batch(req)
+    got, _ = _gpu_optics(ctx, torch, req)
+    _compare(ref, got, "edge cells", floor=_geometric_scale(req))
+
+
+def test_invalid_optics_rejected(ctx, torch):
+    from paper_2409_00165_amd import fos
+    req = W.optics_request(W.single_slab_23())
+    req["r"] = req["r"].copy(); req["r"][5] = -0.1
+    with pytest.raises(fos.FosError) as ei:
+        _gpu_optics(ctx, torch, req)
+    assert ei.value.status == 1 and "cell 5" in str(ei.value) and "r (" in str(ei.value)

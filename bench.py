@@ -120,7 +120,7 @@ def cpu_baseline(wl, optics_host, seconds_target: float):
     o, dt = run(2000)                       # calibration
     rate = max(o[:, 5].sum() / max(dt, 1e-9), 1.0)
     steps_per_photon = o[:, 5].sum() / (2000 * len(idx))
-    n = int(max(2000, min(1_000_000, seconds_target * rate / (steps_per_photon * len(idx)))))
+    n = int(max(2000, min(4_000_000, seconds_target * rate / (steps_per_photon * len(idx)))))
     o, dt = run(n)
     steps = float(o[:, 5].sum())
     return {"value": steps / dt, "unit": "photon-steps/s", "cores": threads, "kind": "oracle",
@@ -129,7 +129,79 @@ def cpu_baseline(wl, optics_host, seconds_target: float):
             "cpu": _cpu_model(), "photons_per_s": len(idx) * n / dt}
 
 
+def sweep_main(args):
+    """Batched sweep: N three-layer designs x 100 wavelengths with uneven photon
+    budgets (log-uniform 1e4..1e6 per design) in one persistent launch,
+    autotuned, captured once as a graph and replayed per step."""
+    def say(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    say("sweep start")
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    say("torch ready")
+    wl = W.stacks_3layer(n_designs=args.designs)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    prob, _ = gpu_problem(h, wl)
+    torch.cuda.synchronize()
+    I = prob.n_items
+    say(f"GPU optics done for {I} items")
+    fos.fos_mc_prepare(h, prob)
+    say("prepared")
+    best, tune_ms = fos.fos_mc_autotune(h, seed=7, photon_cap=2000)
+    print(f"[bench] {I} items; autotuned launch {best} ({tune_ms:.2f} ms at 2000 photons/item)",
+          file=sys.stderr, flush=True)
+    tal = torch.zeros(I * fos.N_TALLY, dtype=torch.int64, device=dev)
+    fos.fos_mc_graph_capture(h, tal)
+    say("graph captured")
+    for w in range(args.warmup):
+        fos.fos_mc_graph_launch(h, args.seed + 1000 + w)
+        torch.cuda.synchronize()
+        say(f"warm-up sweep {w} done")
+    stream = torch.cuda.current_stream()
+    steps_total = 0.0
+    walk_ms = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fos.fos_mc_graph_launch(h, args.seed + k)
+        b.record(stream)
+        b.synchronize()
+        walk_ms.append(a.elapsed_time(b))
+        steps_total += float(tal.cpu().numpy().reshape(I, fos.N_TALLY)[:, 5].sum())
+        print(f"[bench] sweep step {k} {walk_ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    photons = float(W.item_geometry(wl)["photons"].sum())
+    rec = {
+        "metric": "photon-steps/s (batched three-layer design sweep, uneven photon budgets)",
+        "value": steps_total / (sum(walk_ms) / 1e3), "unit": "photon-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(np.mean(walk_ms)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded designs, analytic materials; optics on the GPU)",
+        "config": {"workload": f"stacks_3layer: {args.designs} designs x 100 wavelengths, 3 layers on a "
+                               "3.5+0.01i substrate, photons log-uniform 1e4..1e6 per design",
+                   "items": I, "photons_per_step": photons, "launch": best, "graph": True},
+        "photons_per_s": photons * args.steps / (sum(walk_ms) / 1e3),
+        "design_spectra_per_s": args.designs * args.steps / (sum(walk_ms) / 1e3),
+        "mean_steps_per_photon": steps_total / (photons * args.steps),
+        "wall_s": elapsed,
+        "roofline": {"bound": "alu", "achieved": STEP_SLOTS * steps_total / (sum(walk_ms) / 1e3) / 1e12,
+                     "peak": VALU_PEAK / 1e12, "unit": "Tslot/s",
+                     "frac": STEP_SLOTS * steps_total / (sum(walk_ms) / 1e3) / VALU_PEAK, "traffic": None},
+    }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
+    print("[bench] start", file=sys.stderr, flush=True)
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -139,9 +211,17 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
+    ap.add_argument("--workload", default="two_species_500", choices=["two_species_500", "stacks_3layer"],
+                    help="two_species_500 (default, the headline line) or stacks_3layer (batched sweep)")
+    ap.add_argument("--designs", type=int, default=4096, help="designs of the stacks_3layer sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args(argv)
+    if args.workload == "stacks_3layer":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            return 2
+        return sweep_main(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the transport shards by items across GPUs with one tally gather, not built here)",
@@ -154,6 +234,7 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    print("[bench] torch ready", file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
         dst = torch.empty_like(src)

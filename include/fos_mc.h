@@ -147,6 +147,32 @@ fos_status fos_mc_execute(fos_ctx* ctx, uint64_t seed, const fos_mc_launch* laun
 fos_status fos_mc_run(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
                       const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
 
+/* Launch tuning for the prepared problem: walks at most `photon_cap`
+ * photons of every item (0 = all) under a coordinate search over
+ * refill_min x chunk x block_size x blocks_per_cu, times each candidate with
+ * HIP events on `hip_stream` (best of two after a warm-up), and makes the
+ * fastest the context's default.  Tallies do not depend on the launch
+ * configuration, so tuning never changes results.  Synchronises the stream;
+ * uses context-owned scratch.  best (HOST, may be NULL) receives the chosen
+ * configuration and best_ms (HOST, may be NULL) its time. */
+fos_status fos_mc_autotune(fos_ctx* ctx, uint64_t seed, uint64_t photon_cap, fos_mc_launch* best,
+                           float* best_ms, void* hip_stream);
+
+/* Capture the execute sequence of the prepared problem (tally and cursor
+ * reset, persistent walk) into a HIP graph owned by the context, writing to
+ * `tallies` (DEVICE uint64 [n_items * FOS_N_TALLY]) with launch `launch`
+ * (NULL = defaults).  The graph reads its seed from context memory, so one
+ * captured sweep is replayed with any seed.  Replaces a previous graph.
+ * Uses a context-owned capture stream; `hip_stream` orders the capture after
+ * the caller's prior work. */
+fos_status fos_mc_graph_capture(fos_ctx* ctx, const fos_mc_launch* launch, uint64_t* tallies,
+                                void* hip_stream);
+
+/* Replay the captured sweep with `seed` on `hip_stream` (asynchronous; the
+ * seed is set by a kernel, so the call itself may be captured).  Tallies are
+ * bit-identical to fos_mc_execute with the same seed and prepared problem. */
+fos_status fos_mc_graph_launch(fos_ctx* ctx, uint64_t seed, void* hip_stream);
+
 /* Number of items of the prepared problem (0 if none). */
 int32_t fos_mc_prepared_items(const fos_ctx* ctx);
 

@@ -34,10 +34,12 @@ struct PackArgs {
 struct WalkArgs {
     const float4* table;
     int n_items, max_layers, rec_f4;
-    unsigned long long* cursors;
-    uint32_t* cur_item;
+    const unsigned long long* chunk_prefix;   // [n_items + 1] chunks before each item
+    unsigned long long* chunk_counter;        // next global chunk to hand out
     unsigned long long* tallies;
     uint64_t seed;
+    const uint64_t* seed_ptr;     // if non-null the seed is read here (graph replays)
+    uint64_t photon_cap;          // if non-zero, at most this many photons per item
     uint32_t max_steps;
     int chunk;
     int refill_min;
@@ -75,8 +77,9 @@ hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st);
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
-hipError_t launch_reset(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
-                        int n_items, hipStream_t st);
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, hipStream_t st);
+hipError_t launch_chunk_scan(const float4* table, int rec_f4, int n_items, int chunk, uint64_t photon_cap,
+                             unsigned long long* prefix, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st);
 size_t walk_lds_bytes(int block_size, int max_layers);

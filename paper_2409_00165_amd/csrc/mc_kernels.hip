@@ -3,7 +3,8 @@
 //   pack_items    : validate one item per thread and write its packed record
 //                   (entry Fresnel reflectance, refracted cosine, per-layer
 //                   extinction, albedo, HG constants, interface ratios).
-//   reset_run     : zero the caller's tallies and the work cursors.
+//   reset_run     : zero the caller's tallies and the chunk counter.
+//   chunk_scan    : prefix of per-item chunk counts (the work queue).
 //   walk          : the persistent photon walk (one photon per lane).
 //   philox_words / eval_fresnel / eval_hg : thin kernels exposing the device
 //                   building blocks to the test-suite.
@@ -108,21 +109,54 @@ __global__ void pack_items(PackArgs a)
     }
 }
 
-__global__ void reset_run(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
-                          int n_items)
+__global__ void reset_run(unsigned long long* tallies, unsigned long long* counter, int n_items)
 {
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t j = tid; j < (size_t)n_items * kNTally; j += stride) tallies[j] = 0ull;
-    for (size_t j = tid; j < (size_t)n_items; j += stride) cursors[j] = 0ull;
-    if (tid == 0) *cur_item = 0u;
+    if (tid == 0) *counter = 0ull;
+}
+
+// Exclusive prefix of per-item chunk counts ceil(min(N, cap) / chunk), one
+// block of 1024 threads: each thread sums a contiguous run of items, the run
+// totals are scanned in LDS, and a second pass writes the prefix.
+__global__ __launch_bounds__(1024) void chunk_scan(const float4* table, int rf, int n_items, int chunk,
+                                                   uint64_t cap, unsigned long long* prefix)
+{
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (n_items + 1023) / 1024;
+    const int b = t * per;
+    const int e = b + per < n_items ? b + per : n_items;
+    auto chunks_of = [&](int i) -> unsigned long long {
+        const float4 h1 = table[(size_t)i * rf + 1];
+        uint64_t N = (uint64_t)__float_as_uint(h1.x) | ((uint64_t)__float_as_uint(h1.y) << 32);
+        if (cap && N > cap) N = cap;
+        return (N + (uint64_t)chunk - 1) / (uint64_t)chunk;
+    };
+    unsigned long long sum = 0;
+    for (int i = b; i < e; ++i) sum += chunks_of(i);
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = t > 0 ? part[t - 1] : 0ull;
+    for (int i = b; i < e; ++i) {
+        prefix[i] = run;
+        run += chunks_of(i);
+    }
+    if (t == 1023) prefix[n_items] = part[1023];
 }
 
 // ---------------------------------------------------------------------------
 // the persistent walk
 // ---------------------------------------------------------------------------
 // Each wave works on its own: it claims chunks of photons of one item from a
-// global queue (an item cursor plus a per-item photon cursor), stages the
+// global queue (one chunk counter over the items' chunk prefix), stages the
 // item's record into one of kSlots LDS slots of its own, and fills idle lanes
 // with new photons from the chunk.  A lane keeps the parameters of its
 // current layer in registers and re-reads the LDS slot only when it launches
@@ -184,7 +218,8 @@ __global__ void walk(WalkArgs a)
     if (lane < kSlots) slot_item[lane] = -1;
     wave_sync_lds();
 
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint64_t seed = a.seed_ptr ? *a.seed_ptr : a.seed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t max_steps = a.max_steps;
 
     // lane state
@@ -209,25 +244,24 @@ __global__ void walk(WalkArgs a)
                 if (queue_done) break;
                 const int ns = (src_slot + 1) % kSlots;
                 if (ballot64(alive && slot == ns) != 0ull) break;   // slot still draining
-                // claim a chunk: lane 0 walks the item cursor
+                // claim the next global chunk; lane 0 finds its item by
+                // binary search in the chunk prefix
                 int c_item = -1;
                 unsigned long long c_start = 0ull, c_end = 0ull;
                 if (lane == 0) {
-                    for (;;) {
-                        const uint32_t it = __hip_atomic_load(a.cur_item, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                        if (it >= (uint32_t)a.n_items) break;
-                        const float4 h1 = a.table[(size_t)it * rf + 1];
-                        const uint64_t N = (uint64_t)__float_as_uint(h1.x) |
-                                           ((uint64_t)__float_as_uint(h1.y) << 32);
-                        const unsigned long long st = atomicAdd(a.cursors + it, (unsigned long long)a.chunk);
-                        if (st < N) {
-                            c_item = (int)it;
-                            c_start = st;
-                            c_end = (st + (uint64_t)a.chunk < N) ? st + (uint64_t)a.chunk : N;
-                            break;
+                    const unsigned long long kc = atomicAdd(a.chunk_counter, 1ull);
+                    if (kc < a.chunk_prefix[a.n_items]) {
+                        int lo = 0, hi = a.n_items;   // first j in [1, n] with prefix[j] > kc
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (a.chunk_prefix[mid] <= kc) lo = mid; else hi = mid;
                         }
-                        atomicCAS(a.cur_item, it, it + 1u);
+                        const float4 h1 = a.table[(size_t)lo * rf + 1];
+                        uint64_t N = (uint64_t)__float_as_uint(h1.x) | ((uint64_t)__float_as_uint(h1.y) << 32);
+                        if (a.photon_cap && N > a.photon_cap) N = a.photon_cap;
+                        c_item = lo;
+                        c_start = (kc - a.chunk_prefix[lo]) * (unsigned long long)a.chunk;
+                        c_end = (c_start + (uint64_t)a.chunk < N) ? c_start + (uint64_t)a.chunk : N;
                     }
                 }
                 c_item = __builtin_amdgcn_readfirstlane(c_item);
@@ -414,13 +448,19 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_reset(unsigned long long* tallies, unsigned long long* cursors, uint32_t* cur_item,
-                        int n_items, hipStream_t st)
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, hipStream_t st)
 {
     int blocks = (int)(((size_t)n_items * kNTally + 255) / 256);
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(reset_run, dim3(blocks), dim3(256), 0, st, tallies, cursors, cur_item, n_items);
+    hipLaunchKernelGGL(reset_run, dim3(blocks), dim3(256), 0, st, tallies, counter, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_scan(const float4* table, int rec_f4, int n_items, int chunk, uint64_t photon_cap,
+                             unsigned long long* prefix, hipStream_t st)
+{
+    hipLaunchKernelGGL(chunk_scan, dim3(1), dim3(1024), 0, st, table, rec_f4, n_items, chunk, photon_cap, prefix);
     return hipGetLastError();
 }
 

@@ -22,9 +22,9 @@ struct fos_ctx {
     bool prepared = false;
     float4* table = nullptr;
     size_t table_bytes = 0;
-    unsigned long long* cursors = nullptr;
-    size_t cursors_n = 0;
-    uint32_t* cur_item = nullptr;            // device, 1 word
+    unsigned long long* chunk_prefix = nullptr;    // [n_items + 1]
+    size_t chunk_prefix_bytes = 0;
+    unsigned long long* chunk_counter = nullptr;   // device, 1 word
     unsigned long long* err_dev = nullptr;   // device, 1 word
     unsigned long long* err_host = nullptr;  // pinned host, 1 word
     fos_mc_launch defaults{};
@@ -37,6 +37,14 @@ struct fos_ctx {
     size_t mie_scratch_bytes = 0;
     unsigned int* nmax_dev = nullptr;        // device, 1 word
     unsigned long long* aux_host = nullptr;  // pinned host, 4 words
+    // tuning and graph
+    unsigned long long* tune_tallies = nullptr;
+    size_t tune_tallies_bytes = 0;
+    unsigned long long* seed_dev = nullptr;  // device, 1 word
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    uint64_t prepare_epoch = 0, graph_epoch = 0;
 };
 
 namespace {
@@ -165,9 +173,10 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     c->defaults.blocks_per_cu = 8;
     c->defaults.max_steps = 100000000ull;
     DeviceGuard g(hip_device);
-    if (hipMalloc(reinterpret_cast<void**>(&c->cur_item), 256) != hipSuccess ||
+    if (hipMalloc(reinterpret_cast<void**>(&c->chunk_counter), 256) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->err_dev), 256) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->nmax_dev), 256) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&c->seed_dev), 256) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->aux_host), 4 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(unsigned long long)) != hipSuccess) {
         fos_destroy(c);
@@ -184,8 +193,8 @@ void fos_destroy(fos_ctx* c)
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
         if (c->table) (void)hipFree(c->table);
-        if (c->cursors) (void)hipFree(c->cursors);
-        if (c->cur_item) (void)hipFree(c->cur_item);
+        if (c->chunk_prefix) (void)hipFree(c->chunk_prefix);
+        if (c->chunk_counter) (void)hipFree(c->chunk_counter);
         if (c->err_dev) (void)hipFree(c->err_dev);
         if (c->err_host) (void)hipHostFree(c->err_host);
         if (c->aux_host) (void)hipHostFree(c->aux_host);
@@ -193,6 +202,11 @@ void fos_destroy(fos_ctx* c)
         if (c->cell_of) (void)hipFree(c->cell_of);
         if (c->mie) (void)hipFree(c->mie);
         if (c->mie_scratch) (void)hipFree(c->mie_scratch);
+        if (c->tune_tallies) (void)hipFree(c->tune_tallies);
+        if (c->seed_dev) (void)hipFree(c->seed_dev);
+        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     }
     delete c;
 }
@@ -237,10 +251,8 @@ fos_status fos_mc_prepare(fos_ctx* c, const fos_mc_problem* p, void* hip_stream)
     const int rf = fos::rec_f4(p->max_layers);
     hipError_t e = grow(c->table, c->table_bytes, (size_t)std::max(p->n_items, 1) * rf * sizeof(float4));
     if (e != hipSuccess) return hip_fail(c, e, "item table");
-    size_t cur_bytes = c->cursors_n * sizeof(unsigned long long);
-    e = grow(c->cursors, cur_bytes, (size_t)std::max(p->n_items, 1) * sizeof(unsigned long long));
-    if (e != hipSuccess) return hip_fail(c, e, "work cursors");
-    c->cursors_n = cur_bytes / sizeof(unsigned long long);
+    e = grow(c->chunk_prefix, c->chunk_prefix_bytes, ((size_t)p->n_items + 1) * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(c, e, "work queue");
     if (p->n_items > 0) {
         if ((e = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess) return hip_fail(c, e, "reset");
         fos::PackArgs a{p->n_items, p->max_layers, p->n_layers, p->mu_s, p->mu_a, p->g, p->n_layer,
@@ -262,7 +274,36 @@ fos_status fos_mc_prepare(fos_ctx* c, const fos_mc_problem* p, void* hip_stream)
     c->n_items = p->n_items;
     c->max_layers = p->max_layers;
     c->prepared = true;
+    c->prepare_epoch++;
     return FOS_OK;
+}
+
+// Zero the tallies and the chunk counter, then rebuild the chunk prefix for
+// this launch's chunk size and photon cap (kernels only: graph-capturable).
+static hipError_t enqueue_queue_reset(fos_ctx* c, unsigned long long* tal, int chunk, uint64_t cap, hipStream_t st)
+{
+    hipError_t e = fos::launch_reset(tal, c->chunk_counter, c->n_items, st);
+    if (e != hipSuccess) return e;
+    return fos::launch_chunk_scan(c->table, fos::rec_f4(c->max_layers), c->n_items, chunk, cap, c->chunk_prefix, st);
+}
+
+static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed, unsigned long long* tal)
+{
+    fos::WalkArgs a{};
+    a.table = c->table;
+    a.n_items = c->n_items;
+    a.max_layers = c->max_layers;
+    a.rec_f4 = fos::rec_f4(c->max_layers);
+    a.chunk_prefix = c->chunk_prefix;
+    a.chunk_counter = c->chunk_counter;
+    a.tallies = tal;
+    a.seed = seed;
+    a.seed_ptr = nullptr;
+    a.photon_cap = 0;
+    a.max_steps = (uint32_t)L.max_steps;
+    a.chunk = L.chunk;
+    a.refill_min = L.refill_min;
+    return a;
 }
 
 fos_status fos_mc_execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies,
@@ -279,23 +320,132 @@ fos_status fos_mc_execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch
     DeviceGuard g(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
-    hipError_t e = fos::launch_reset(tal, c->cursors, c->cur_item, c->n_items, st);
-    if (e != hipSuccess) return hip_fail(c, e, "reset kernel");
-    fos::WalkArgs a{};
-    a.table = c->table;
-    a.n_items = c->n_items;
-    a.max_layers = c->max_layers;
-    a.rec_f4 = fos::rec_f4(c->max_layers);
-    a.cursors = c->cursors;
-    a.cur_item = c->cur_item;
-    a.tallies = tal;
-    a.seed = seed;
-    a.max_steps = (uint32_t)L.max_steps;
-    a.chunk = L.chunk;
-    a.refill_min = L.refill_min;
+    hipError_t e = enqueue_queue_reset(c, tal, L.chunk, 0, st);
+    if (e != hipSuccess) return hip_fail(c, e, "reset kernels");
+    const fos::WalkArgs a = walk_args(c, L, seed, tal);
     const int grid = c->n_cu * L.blocks_per_cu;
     if ((e = fos::launch_walk(a, grid, L.block_size, st)) != hipSuccess) return hip_fail(c, e, "walk kernel");
     return FOS_OK;
+}
+
+fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_mc_launch* best,
+                           float* best_ms, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!c->prepared) return fail(c, FOS_E_NOT_PREPARED, "no prepared problem (call fos_mc_prepare)");
+    if (c->n_items == 0) {
+        if (best) *best = c->defaults;
+        if (best_ms) *best_ms = 0.f;
+        return FOS_OK;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = grow(c->tune_tallies, c->tune_tallies_bytes,
+                        (size_t)c->n_items * fos::kNTally * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(c, e, "tuning scratch");
+    hipEvent_t ev0, ev1;
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+        return fail(c, FOS_E_DEVICE, "event creation failed");
+    auto time_one = [&](const fos_mc_launch& L, float& ms) -> hipError_t {
+        fos::WalkArgs a = walk_args(c, L, seed, c->tune_tallies);
+        a.photon_cap = photon_cap;
+        const int grid = c->n_cu * L.blocks_per_cu;
+        float bestv = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipError_t r;
+            if ((r = enqueue_queue_reset(c, c->tune_tallies, L.chunk, photon_cap, st)) != hipSuccess) return r;
+            if ((r = hipEventRecord(ev0, st)) != hipSuccess) return r;
+            if ((r = fos::launch_walk(a, grid, L.block_size, st)) != hipSuccess) return r;
+            if ((r = hipEventRecord(ev1, st)) != hipSuccess) return r;
+            if ((r = hipEventSynchronize(ev1)) != hipSuccess) return r;
+            float t = 0.f;
+            if ((r = hipEventElapsedTime(&t, ev0, ev1)) != hipSuccess) return r;
+            if (rep > 0 && t < bestv) bestv = t;   // first run is a warm-up
+        }
+        ms = bestv;
+        return hipSuccess;
+    };
+    fos_mc_launch cur = c->defaults;
+    float cur_ms = 0.f;
+    e = time_one(cur, cur_ms);
+    const int32_t refills[] = {4, 6, 8, 12, 16};
+    const int32_t chunks[] = {1024, 2048, 4096, 8192};
+    const int32_t blocks[] = {128, 256, 512};
+    const int32_t per_cu[] = {8, 16};
+    for (int knob = 0; knob < 4 && e == hipSuccess; ++knob) {
+        const int32_t* vals = knob == 0 ? refills : knob == 1 ? chunks : knob == 2 ? blocks : per_cu;
+        const int nv = knob == 0 ? 5 : knob == 1 ? 4 : knob == 2 ? 3 : 2;
+        for (int i = 0; i < nv && e == hipSuccess; ++i) {
+            fos_mc_launch L = cur;
+            if (knob == 0) L.refill_min = vals[i];
+            if (knob == 1) L.chunk = vals[i];
+            if (knob == 2) L.block_size = vals[i];
+            if (knob == 3) L.blocks_per_cu = vals[i];
+            if (std::memcmp(&L, &cur, sizeof L) == 0) continue;
+            float ms = 0.f;
+            e = time_one(L, ms);
+            if (e == hipSuccess && ms < cur_ms) { cur = L; cur_ms = ms; }
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune");
+    c->defaults = cur;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return FOS_OK;
+}
+
+fos_status fos_mc_graph_capture(fos_ctx* c, const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!c->prepared) return fail(c, FOS_E_NOT_PREPARED, "no prepared problem (call fos_mc_prepare)");
+    if (c->n_items > 0 && !tallies) return fail(c, FOS_E_INVALID_ARG, "tallies is NULL");
+    const fos_mc_launch L = merge(c->defaults, launch);
+    fos_status s = check_launch(c, L);
+    if (s != FOS_OK) return s;
+    DeviceGuard g(c->device);
+    hipError_t e;
+    if (!c->capture_stream && (e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(c, e, "capture stream");
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    // order the capture after the caller's work (the prepared table)
+    if ((e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(hip_stream))) != hipSuccess)
+        return hip_fail(c, e, "graph capture");
+    unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
+    if ((e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(c, e, "begin capture");
+    hipError_t e1 = hipSuccess;
+    if (c->n_items > 0) {
+        fos::WalkArgs a = walk_args(c, L, 0, tal);
+        a.seed_ptr = reinterpret_cast<const uint64_t*>(c->seed_dev);
+        e1 = enqueue_queue_reset(c, tal, L.chunk, 0, c->capture_stream);
+        if (e1 == hipSuccess) e1 = fos::launch_walk(a, c->n_cu * L.blocks_per_cu, L.block_size, c->capture_stream);
+    }
+    e = hipStreamEndCapture(c->capture_stream, &c->graph);
+    if (e1 != hipSuccess) return hip_fail(c, e1, "graph capture launch");
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    if ((e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(c, e, "graph instantiate");
+    c->graph_epoch = c->prepare_epoch;
+    return FOS_OK;
+}
+
+fos_status fos_mc_graph_launch(fos_ctx* c, uint64_t seed, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!c->graph_exec) return fail(c, FOS_E_NOT_PREPARED, "no captured graph (call fos_mc_graph_capture)");
+    if (c->graph_epoch != c->prepare_epoch)
+        return fail(c, FOS_E_NOT_PREPARED, "problem re-prepared since the graph was captured");
+    DeviceGuard g(c->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = fos::launch_fill_u64(c->seed_dev, (unsigned long long)seed, 1, st);
+    if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, st);
+    return e == hipSuccess ? FOS_OK : hip_fail(c, e, "graph launch");
 }
 
 fos_status fos_mc_run(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const fos_mc_launch* launch,

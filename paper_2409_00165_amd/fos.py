@@ -83,6 +83,13 @@ def lib():
         L.fos_mc_get_launch.restype = c_int
         L.fos_mc_set_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
         L.fos_mc_set_launch.restype = c_int
+        L.fos_mc_autotune.argtypes = [c_void_p, c_uint64, c_uint64, POINTER(fos_mc_launch), POINTER(c_float),
+                                      c_void_p]
+        L.fos_mc_autotune.restype = c_int
+        L.fos_mc_graph_capture.argtypes = [c_void_p, POINTER(fos_mc_launch), c_void_p, c_void_p]
+        L.fos_mc_graph_capture.restype = c_int
+        L.fos_mc_graph_launch.argtypes = [c_void_p, c_uint64, c_void_p]
+        L.fos_mc_graph_launch.restype = c_int
         L.fos_optics_run.argtypes = [c_void_p, POINTER(fos_optics_problem), c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]
         L.fos_optics_run.restype = c_int
@@ -225,6 +232,25 @@ def fos_mc_run(ctx, problem: MCProblem, seed: int, tallies, launch=None, stream=
     _ptr(tallies, None, problem.n_items * N_TALLY)
     _check(ctx, lib().fos_mc_run(ctx, ctypes.byref(problem.struct), c_uint64(seed), _launch(launch),
                                  _ptr(tallies), _stream(stream)))
+
+
+def fos_mc_autotune(ctx, seed: int = 1, photon_cap: int = 0, stream=None):
+    """Tune the launch on the prepared problem; returns (launch dict, ms)."""
+    best = fos_mc_launch()
+    ms = c_float()
+    _check(ctx, lib().fos_mc_autotune(ctx, c_uint64(seed), c_uint64(photon_cap), ctypes.byref(best),
+                                      ctypes.byref(ms), _stream(stream)))
+    return best.as_dict(), ms.value
+
+
+def fos_mc_graph_capture(ctx, tallies, launch=None, stream=None) -> None:
+    n = fos_mc_prepared_items(ctx)
+    _check(ctx, lib().fos_mc_graph_capture(ctx, _launch(launch), _ptr(tallies, None, n * N_TALLY),
+                                           _stream(stream)))
+
+
+def fos_mc_graph_launch(ctx, seed: int, stream=None) -> None:
+    _check(ctx, lib().fos_mc_graph_launch(ctx, c_uint64(seed), _stream(stream)))
 
 
 def fos_mc_prepared_items(ctx) -> int:

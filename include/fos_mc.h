@@ -173,6 +173,13 @@ fos_status fos_mc_graph_capture(fos_ctx* ctx, const fos_mc_launch* launch, uint6
  * bit-identical to fos_mc_execute with the same seed and prepared problem. */
 fos_status fos_mc_graph_launch(fos_ctx* ctx, uint64_t seed, void* hip_stream);
 
+/* (R, A, T) fractions from tallies: rat[3i..3i+2] = ((specular + diffuse)/N,
+ * absorbed/N, transmitted/N) with N the photons of item i (the paper's
+ * reflectance, absorptance and transmittance, Methodology, Photon
+ * transport).  tallies DEVICE uint64 [n * FOS_N_TALLY], rat DEVICE float
+ * [n * 3].  Asynchronous. */
+fos_status fos_mc_fractions(fos_ctx* ctx, int32_t n, const uint64_t* tallies, float* rat, void* hip_stream);
+
 /* Number of items of the prepared problem (0 if none). */
 int32_t fos_mc_prepared_items(const fos_ctx* ctx);
 
@@ -220,6 +227,102 @@ typedef struct {
  * FOS_E_INVALID_ARG names the first bad cell. */
 fos_status fos_optics_run(fos_ctx* ctx, const fos_optics_problem* problem, float* mu_s, float* mu_a,
                           float* g, double* out_f64, void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Surrogate network (the paper's neural-network alternative to Monte Carlo,  */
+/* Methodology, Photon transport; trained here on this library's own walk)    */
+/* ------------------------------------------------------------------------- */
+
+#define FOS_SUR_FEATURES 8
+#define FOS_SUR_MEMBERS 4
+#define FOS_SUR_PARAMS 200451    /* fp32 parameters per ensemble member */
+
+/* Training options.  The network of every member is 8 standardised inputs ->
+ * 4 hidden layers of 256 with tanh-form GELU -> 3 logits -> softmax (R, A,
+ * T); bf16 operands on the matrix cores with fp32 accumulation and fp32
+ * master weights; loss = cross-entropy against the Monte Carlo fractions;
+ * Adam (0.9, 0.999, 1e-8) with a cosine learning-rate decay. */
+typedef struct {
+    int32_t epochs;        /* passes over the data, >= 1 */
+    int32_t batch;         /* rows per step and member, a multiple of 64 */
+    float lr;              /* peak learning rate */
+    float lr_min;          /* final learning rate of the cosine decay */
+    uint64_t seed;         /* He initialisation and per-member shuffles */
+    int32_t resume;        /* 1: continue from the context's model and optimiser state */
+    float* loss_history;   /* DEVICE [epochs * 4] mean loss per epoch and member, or NULL */
+} fos_train_opts;
+
+/* The 8 raw surrogate features of every item of a transport problem
+ * (DEVICE arrays as in fos_mc_problem, layer 0 of each item):
+ * log10(mu_s t + 1e-6), log10(mu_a t + 1e-6), g, n_layer, n_lower,
+ * log10(k_lower + 1e-4), mu0, layer index (0).  x DEVICE float [n_items * 8];
+ * eligible DEVICE uint8 [n_items] (may be NULL) = 1 for single-layer items
+ * lit from an upper medium of index 1 -- the only items the surrogate serves
+ * (the paper's network likewise needs air or vacuum boundaries).
+ * Asynchronous. */
+fos_status fos_sur_features(fos_ctx* ctx, const fos_mc_problem* problem, float* x, uint8_t* eligible,
+                            void* hip_stream);
+
+/* Train the 4-member ensemble on n rows: x DEVICE float [n * 8] raw
+ * features, y DEVICE float [n * 3] Monte Carlo (R, A, T) fractions.  Unless
+ * resuming, computes the feature mean/std (standardisation) and min/max (the
+ * validity box of fos_sur_predict), initialises the members from `seed` and
+ * zeroes the optimiser.  Each member sees its own shuffle of the rows every
+ * epoch.  Enqueued on `hip_stream` (the call returns before the work ends);
+ * n must be >= batch. */
+fos_status fos_sur_train(fos_ctx* ctx, const float* x, const float* y, int64_t n, const fos_train_opts* opts,
+                         void* hip_stream);
+
+/* Ensemble prediction and gate for n rows of raw features x (DEVICE float
+ * [n * 8]): rat (DEVICE float [n * 3]) = member mean of (R, A, T); spread
+ * (DEVICE float [n]) = max over channels of (max - min across members);
+ * in_domain (DEVICE uint8 [n]) = 1 if every feature lies inside the training
+ * box and eligible[i] (DEVICE uint8, may be NULL) is set; members (DEVICE
+ * float [4 * n * 3], may be NULL) = each member's prediction.  Any output may
+ * be NULL.  Asynchronous. */
+fos_status fos_sur_predict(fos_ctx* ctx, const float* x, const uint8_t* eligible, int64_t n, float* rat,
+                           float* spread, uint8_t* in_domain, float* members, void* hip_stream);
+
+/* Test hook: gradient of the mean loss over the first n rows (n a multiple
+ * of 64, no shuffle) for every member, without updating: grads DEVICE float
+ * [4 * FOS_SUR_PARAMS] in the flat layout of fos_sur_save (W1 [8][256], b1,
+ * W2 [256][256], b2, W3, b3, W4, b4, W5 [256][3], b5), loss DEVICE float [4]. */
+fos_status fos_sur_grad(fos_ctx* ctx, const float* x, const float* y, int64_t n, float* grads, float* loss,
+                        void* hip_stream);
+
+/* Serialise the model (and optimiser state) to HOST memory.  With blob NULL
+ * only *bytes is set to the size needed.  Layout (little endian): 8-byte
+ * magic "FOSSUR01", uint32 members, features, hidden, params, has_opt,
+ * adam_step, then float32 stats [32] (mean, 1/std, min, max of the 8
+ * features), params [members * params], and if has_opt Adam m and v. */
+fos_status fos_sur_save(const fos_ctx* ctx, void* blob, size_t* bytes);
+
+/* Load a model written by fos_sur_save (HOST blob; copies). */
+fos_status fos_sur_load(fos_ctx* ctx, const void* blob, size_t bytes);
+
+/* Surrogate design sweep with Monte Carlo fallback.  For every item of
+ * `problem` (DEVICE arrays as for fos_mc_run): features, ensemble prediction
+ * and gate (fos_sur_features, fos_sur_predict); items that are ineligible,
+ * outside the training box or whose ensemble spread exceeds `spread_max` are
+ * compacted and walked by the Monte Carlo path with `fallback_photons`
+ * photons each under `seed` (stream id = position in the compacted list),
+ * and their fractions replace the prediction.  Outputs (DEVICE): rat float
+ * [n * 3] = (R, A, T); spread float [n] (may be NULL); used_mc uint8 [n].
+ * *n_fallback (HOST, may be NULL) = number of Monte Carlo items.  Replaces
+ * the context's prepared transport problem; synchronises `hip_stream` to
+ * size the fallback batch. */
+fos_status fos_sweep_run(fos_ctx* ctx, const fos_mc_problem* problem, float spread_max, uint64_t fallback_photons,
+                         uint64_t seed, float* rat, float* spread, uint8_t* used_mc, int64_t* n_fallback,
+                         void* hip_stream);
+
+/* Spectral reductions of a sweep (the paper's solar-weighted integral,
+ * eq. (21), and band emittance): for each design d of `designs` rows of
+ * `lambdas` wavelengths, out[2d] = sum_l w_r[l] R[d][l] and out[2d+1] =
+ * sum_l w_e[l] A[d][l] (by Kirchhoff's law the absorptance is the
+ * emittance).  rat DEVICE float [designs * lambdas * 3]; weights DEVICE float
+ * [lambdas] (normalised quadrature weights); out DEVICE float [2 designs]. */
+fos_status fos_spectral_reduce(fos_ctx* ctx, int32_t designs, int32_t lambdas, const float* rat, const float* w_r,
+                               const float* w_e, float* out, void* hip_stream);
 
 /* Raw Philox4x32-10 words for testing the generator: out[4*j + w] =
  * word w of counter (p lo, p hi, step, stream) with p = photon[j],

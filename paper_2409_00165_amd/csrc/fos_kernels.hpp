@@ -82,6 +82,7 @@ hipError_t launch_chunk_scan(const float4* table, int rec_f4, int n_items, int c
                              unsigned long long* prefix, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st);
+hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st);
 size_t walk_lds_bytes(int block_size, int max_layers);
 hipError_t launch_philox_words(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
                                uint64_t seed, uint32_t* out, hipStream_t st);

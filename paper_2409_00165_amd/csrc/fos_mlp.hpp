@@ -1,0 +1,147 @@
+// fos_mlp.hpp -- layout of the surrogate network's parameters and the
+// argument blocks of its kernels (mlp_kernels.hip), shared with the host
+// runtime (surrogate.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fos {
+
+constexpr int kFeatures = 8;     // network inputs
+constexpr int kHidden = 256;     // width of the 4 hidden layers
+constexpr int kNets = 4;         // ensemble members
+constexpr int kPadIn = 64;       // bf16 copy of the inputs, padded for the W1 gradient GEMM
+constexpr int kPadOut = 64;      // logits / logit-gradient rows padded to one GEMM tile
+constexpr int kPadK5 = 32;       // W5 padded on the class axis for the dH4 GEMM
+
+// flat fp32 parameters of one member: W1 [8][256], b1, W2 [256][256], b2,
+// W3, b3, W4, b4, W5 [256][3], b5 (W[k_in][n_out], row-major)
+constexpr size_t kOffW1 = 0;
+constexpr size_t kOffB1 = kOffW1 + (size_t)kFeatures * kHidden;
+constexpr size_t kOffW2 = kOffB1 + kHidden;
+constexpr size_t kOffB2 = kOffW2 + (size_t)kHidden * kHidden;
+constexpr size_t kOffW3 = kOffB2 + kHidden;
+constexpr size_t kOffB3 = kOffW3 + (size_t)kHidden * kHidden;
+constexpr size_t kOffW4 = kOffB3 + kHidden;
+constexpr size_t kOffB4 = kOffW4 + (size_t)kHidden * kHidden;
+constexpr size_t kOffW5 = kOffB4 + kHidden;
+constexpr size_t kOffB5 = kOffW5 + (size_t)kHidden * 3;
+constexpr size_t kParams = kOffB5 + 3;   // 200,451
+
+// bf16 copies of one member: W2, W3, W4 [256][256], W5p [256][64] (W5 with
+// zero columns 3..63), W5t [256][32] (W5 with zero columns 3..31)
+constexpr size_t kBfW2 = 0;
+constexpr size_t kBfW3 = kBfW2 + (size_t)kHidden * kHidden;
+constexpr size_t kBfW4 = kBfW3 + (size_t)kHidden * kHidden;
+constexpr size_t kBfW5p = kBfW4 + (size_t)kHidden * kHidden;
+constexpr size_t kBfW5t = kBfW5p + (size_t)kHidden * kPadOut;
+constexpr size_t kBfParams = kBfW5t + (size_t)kHidden * kPadK5;
+
+enum Epilogue : int { kEpiStore = 0, kEpiBiasGelu = 1, kEpiGeluGrad = 2 };
+
+struct GemmArgs {
+    int M, N, K;
+    const __bf16* A; long lda; long strideA;
+    const __bf16* B; long ldb; long strideB;
+    float* Cf; long ldc; long strideC;     // fp32 output (may be null for BiasGelu/GeluGrad)
+    __bf16* Cb; long strideCb;             // bf16 output, leading dimension ldc
+    const float* bias; long strideBias;    // BiasGelu
+    const float* Z; long strideZ;          // GeluGrad: saved pre-activation, leading dimension ldc
+};
+
+struct StdArgs {
+    const float* x;            // raw features [n_src][8]
+    int64_t n_src, base;
+    int rows, rows_pad;
+    const uint64_t* perm_mul;  // per member (training gather) or null
+    const uint64_t* perm_add;
+    const float* mean;
+    const float* inv_std;
+    float* xs;                 // [nets][rows_pad][8]
+    __bf16* xb;                // [nets][rows_pad][64] or null
+    const float* y;            // [n_src][3] or null
+    float* ys;                 // [nets][rows_pad][3] or null
+};
+
+struct SoftmaxArgs {
+    int rows, rows_pad;
+    const float* params; size_t pstride;
+    const float* logits;       // [nets][rows_pad][64]
+    float* probs;              // [nets][rows_pad][3]
+    const float* ys;           // targets or null (inference)
+    float* loss_rows;          // [nets][rows_pad]
+    __bf16* dlog;              // [nets][rows_pad][64]
+    float* dlog_f;             // [nets][rows_pad][3]
+    float inv_batch;
+};
+
+struct AdamArgs {
+    float* w; float* m; float* v;
+    const float* grads;
+    __bf16* wb;
+    float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t)
+};
+
+struct GateArgs {
+    int rows, rows_pad, nets;
+    int64_t out_offset, n_total;
+    const float* probs;          // [nets][rows_pad][3]
+    const float* x;              // raw features of these rows [rows][8]
+    const uint8_t* eligible;     // or null
+    const float* lo; const float* hi;
+    float* rat; float* spread; uint8_t* in_domain; float* members;
+};
+
+// sweep: fallback selection, compaction, gather/scatter of sub-problems
+struct SweepSelectArgs {
+    int64_t n;
+    const float* spread; const uint8_t* in_domain;
+    float spread_max;
+    uint8_t* used_mc;               // fallback flag per item
+    unsigned long long* block_count; // [blocks]
+    unsigned long long* block_offset;
+    int64_t* idx;                   // compacted item indices
+};
+constexpr int kSelectPerBlock = 2048;   // 256 threads x 8 items
+
+struct GatherArgs {
+    int64_t m; int L;
+    const int64_t* idx;
+    const int32_t* n_layers; const float *mu_s, *mu_a, *g, *n_layer, *thickness;
+    const float *n_upper, *n_lower, *k_lower, *mu0;
+    int32_t* o_n_layers; float *o_mu_s, *o_mu_a, *o_g, *o_n_layer, *o_thickness;
+    float *o_n_upper, *o_n_lower, *o_k_lower, *o_mu0; uint64_t* o_photons;
+    uint64_t photons;
+};
+
+hipError_t launch_select_count(const SweepSelectArgs& a, hipStream_t st);
+hipError_t launch_select_scan(const SweepSelectArgs& a, unsigned long long* total, hipStream_t st);
+hipError_t launch_select_write(const SweepSelectArgs& a, hipStream_t st);
+hipError_t launch_gather_items(const GatherArgs& a, hipStream_t st);
+hipError_t launch_scatter_mc(int64_t m, const int64_t* idx, const unsigned long long* tallies, float* rat,
+                             hipStream_t st);
+hipError_t launch_spectral_reduce(int designs, int lambdas, const float* rat, const float* w_r, const float* w_e,
+                                  float* out, hipStream_t st);
+
+hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st);
+hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
+                           const float* g, const float* n_layer, const float* thickness, const float* n_upper,
+                           const float* n_lower, const float* k_lower, const float* mu0, float* x,
+                           uint8_t* eligible, hipStream_t st);
+hipError_t launch_standardize(const StdArgs& a, int nets, hipStream_t st);
+hipError_t launch_first_layer(int rows_pad, const float* xs, const float* params, size_t pstride, float* Z1,
+                              __bf16* H1, int nets, hipStream_t st);
+hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st);
+hipError_t launch_colsum(const float* src, int rows, int cols, size_t sstride, float* partial, int chunks,
+                         float* out, size_t ostride, int nets, hipStream_t st);
+hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
+                             size_t dstride, int nets, hipStream_t st);
+hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st);
+hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t st);
+hipError_t launch_ensemble_gate(const GateArgs& a, hipStream_t st);
+hipError_t launch_feature_stats(const float* x, int64_t n, float* stats, hipStream_t st);
+hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st);
+
+}  // namespace fos

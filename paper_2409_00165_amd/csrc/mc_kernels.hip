@@ -476,6 +476,30 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, h
     return hipGetLastError();
 }
 
+// (R, A, T) fractions of every item from its tallies: R = (specular +
+// diffuse)/N, A/N, T/N with N the item's photons
+__global__ void fractions_k(int n, const unsigned long long* t, float* rat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long* ti = t + (size_t)i * kNTally;
+    const double N = (double)(ti[0] + ti[1] + ti[2] + ti[3] + ti[4]);
+    if (N == 0.0) {
+        rat[3 * (size_t)i + 0] = rat[3 * (size_t)i + 1] = rat[3 * (size_t)i + 2] = 0.0f;
+        return;
+    }
+    rat[3 * (size_t)i + 0] = (float)((double)(ti[0] + ti[1]) / N);
+    rat[3 * (size_t)i + 1] = (float)((double)ti[2] / N);
+    rat[3 * (size_t)i + 2] = (float)((double)ti[3] / N);
+}
+
+hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fractions_k, dim3((n + 255) / 256), dim3(256), 0, st, n, tallies, rat);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // test hooks
 // ---------------------------------------------------------------------------

@@ -1,0 +1,673 @@
+// mlp_kernels.hip -- the surrogate network on gfx950: a small MLP that maps a
+// single-layer transport problem to its R/A/T fractions, standing in for the
+// Monte Carlo walk the way the paper's pre-trained network does
+// (Methodology, Photon transport), with the walk as its fallback.
+//
+// Network (per ensemble member): 8 standardised features -> 256 -> 256 ->
+// 256 -> 256 (tanh-form GELU after each) -> 3 logits -> softmax.
+//
+//   gemm<TA,TB,EPI> : C = op(A) op(B), bf16 operands on v_mfma_f32_16x16x32_bf16,
+//                     fp32 accumulation, 64x64x32 LDS tiles, fused epilogues
+//                     (store fp32 / bias + GELU -> fp32 Z and bf16 H /
+//                     multiply by GELU'(Z) -> fp32 and bf16 dZ); grid.z walks
+//                     the ensemble members.
+//   features        : transport problem -> the 8 raw features.
+//   standardize     : raw features -> standardised fp32 rows (+ bf16 padded
+//                     copy for the first layer's weight gradient), optional
+//                     per-member gather of a training batch.
+//   first_layer     : the 8-wide input layer on the VALU (fp32).
+//   softmax_ce      : softmax of the 3 logits, cross-entropy against the Monte
+//                     Carlo fractions, d loss / d logits = (p - y) / B.
+//   colsum          : bias gradients (two-stage, deterministic).
+//   adam            : Adam on fp32 master weights, refreshing bf16 copies.
+//   ensemble_gate   : member mean, spread (max over channels of max - min),
+//                     training-box domain test.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fos_mlp.hpp"
+
+namespace fos {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
+constexpr float kGeluA = 0.044715f;
+
+__device__ __forceinline__ float tanh_fast(float u)
+{
+    // tanh(u) = 1 - 2 / (1 + e^{2u}); saturates correctly at +-inf
+    const float e = __expf(2.0f * u);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
+}
+__device__ __forceinline__ float gelu_f(float z)
+{
+    return 0.5f * z * (1.0f + tanh_fast(kGeluC * fmaf(kGeluA * z, z * z, z)));
+}
+__device__ __forceinline__ float gelu_grad_f(float z)
+{
+    const float t = tanh_fast(kGeluC * fmaf(kGeluA * z, z * z, z));
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * kGeluC * fmaf(3.0f * kGeluA, z * z, 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM
+// ---------------------------------------------------------------------------
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[kBM][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kBN][kBK + kPad];
+    const int net = blockIdx.z;
+    const __bf16* A = g.A + (size_t)net * g.strideA;
+    const __bf16* B = g.B + (size_t)net * g.strideB;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        if (!TA) {   // A(m,k) = A[m*lda + k]
+            const int r = tid >> 2, kc = (tid & 3) * 8;
+            *reinterpret_cast<bf16x8*>(&As[r][kc]) =
+                *reinterpret_cast<const bf16x8*>(A + (size_t)(m0 + r) * g.lda + k0 + kc);
+        } else {     // A(m,k) = A[k*lda + m]
+            const int kk = tid >> 3, mc = (tid & 7) * 8;
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + (size_t)(k0 + kk) * g.lda + m0 + mc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[mc + j][kk] = v[j];
+        }
+        if (TB) {    // B(k,n) = B[n*ldb + k]
+            const int r = tid >> 2, kc = (tid & 3) * 8;
+            *reinterpret_cast<bf16x8*>(&Bs[r][kc]) =
+                *reinterpret_cast<const bf16x8*>(B + (size_t)(n0 + r) * g.ldb + k0 + kc);
+        } else {     // B(k,n) = B[k*ldb + n]
+            const int kk = tid >> 3, nc = (tid & 7) * 8;
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(B + (size_t)(k0 + kk) * g.ldb + n0 + nc);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bs[nc + j][kk] = v[j];
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    float* Cf = g.Cf ? g.Cf + (size_t)net * g.strideC : nullptr;
+    __bf16* Cb = g.Cb ? g.Cb + (size_t)net * g.strideCb : nullptr;
+    const float* bias = g.bias ? g.bias + (size_t)net * g.strideBias : nullptr;
+    const float* Z = g.Z ? g.Z + (size_t)net * g.strideZ : nullptr;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                const size_t o = (size_t)row * g.ldc + col;
+                const float v = acc[i][j][r];
+                if (EPI == kEpiStore) {
+                    Cf[o] = v;
+                } else if (EPI == kEpiBiasGelu) {
+                    const float z = v + bias[col];
+                    if (Cf) Cf[o] = z;
+                    Cb[o] = (__bf16)gelu_f(z);
+                } else {   // kEpiGeluGrad: v is dH, Z the saved pre-activation
+                    const float dz = v * gelu_grad_f(Z[o]);
+                    if (Cf) Cf[o] = dz;
+                    Cb[o] = (__bf16)dz;
+                }
+            }
+}
+
+template <bool TA, bool TB, int EPI>
+static hipError_t launch_gemm_t(const GemmArgs& g, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), dim3(g.N / kBN, g.M / kBM, nets), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st)
+{
+    if (g.M % kBM || g.N % kBN || g.K % kBK || g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+    if (!ta && !tb && epi == kEpiBiasGelu) return launch_gemm_t<false, false, kEpiBiasGelu>(g, nets, st);
+    if (!ta && !tb && epi == kEpiStore) return launch_gemm_t<false, false, kEpiStore>(g, nets, st);
+    if (!ta && tb && epi == kEpiGeluGrad) return launch_gemm_t<false, true, kEpiGeluGrad>(g, nets, st);
+    if (!ta && tb && epi == kEpiStore) return launch_gemm_t<false, true, kEpiStore>(g, nets, st);
+    if (ta && !tb && epi == kEpiStore) return launch_gemm_t<true, false, kEpiStore>(g, nets, st);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// features, standardisation, first layer
+// ---------------------------------------------------------------------------
+// Raw features of item i (single layer): log10(tau_s + 1e-6),
+// log10(tau_a + 1e-6), g, n_layer, n_lower, log10(k_lower + 1e-4), mu0, 0.
+// eligible = one layer and an upper medium of index 1.
+__global__ void features_kernel(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
+                                const float* g, const float* n_layer, const float* thickness,
+                                const float* n_upper, const float* n_lower, const float* k_lower,
+                                const float* mu0, float* x, uint8_t* eligible)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t o = (size_t)i * L;
+    const float t = thickness[o];
+    float* xi = x + (size_t)i * kFeatures;
+    xi[0] = log10f(mu_s[o] * t + 1e-6f);
+    xi[1] = log10f(mu_a[o] * t + 1e-6f);
+    xi[2] = g[o];
+    xi[3] = n_layer[o];
+    xi[4] = n_lower[i];
+    xi[5] = log10f(k_lower[i] + 1e-4f);
+    xi[6] = mu0[i];
+    xi[7] = 0.0f;
+    if (eligible) eligible[i] = (n_layers[i] == 1 && n_upper[i] == 1.0f) ? 1 : 0;
+}
+
+// row r of member m takes source row idx = perm(m, r) (or r), standardised
+__global__ void standardize_kernel(StdArgs a)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (r >= a.rows) return;
+    int64_t src = a.base + r;
+    if (a.perm_mul) src = (int64_t)(((uint64_t)a.perm_mul[m] * (uint64_t)(a.base + r) + a.perm_add[m]) % (uint64_t)a.n_src);
+    const bool valid = src < a.n_src;
+    float* xs = a.xs + ((size_t)m * a.rows_pad + r) * kFeatures;
+    __bf16* xb = a.xb ? a.xb + ((size_t)m * a.rows_pad + r) * kPadIn : nullptr;
+    for (int k = 0; k < kFeatures; ++k) {
+        const float v = valid ? (a.x[(size_t)src * kFeatures + k] - a.mean[k]) * a.inv_std[k] : 0.0f;
+        xs[k] = v;
+        if (xb) xb[k] = (__bf16)v;
+    }
+    if (xb)
+        for (int k = kFeatures; k < kPadIn; ++k) xb[k] = (__bf16)0.0f;
+    if (a.y && a.ys) {
+        float* ys = a.ys + ((size_t)m * a.rows_pad + r) * 3;
+        for (int c = 0; c < 3; ++c) ys[c] = valid ? a.y[(size_t)src * 3 + c] : 0.0f;
+    }
+}
+
+// Z1 = X W1 + b1 (fp32, K = 8), H1 = bf16(gelu(Z1)); one thread per output
+__global__ void first_layer_kernel(int rows_pad, const float* xs, const float* params, size_t pstride,
+                                   float* Z1, __bf16* H1)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (idx >= (size_t)rows_pad * kHidden) return;
+    const int r = (int)(idx / kHidden), n = (int)(idx % kHidden);
+    const float* P = params + (size_t)m * pstride;
+    const float* x = xs + ((size_t)m * rows_pad + r) * kFeatures;
+    float z = P[kOffB1 + n];
+#pragma unroll
+    for (int k = 0; k < kFeatures; ++k) z = fmaf(x[k], P[kOffW1 + k * kHidden + n], z);
+    const size_t o = (size_t)m * rows_pad * kHidden + idx;
+    if (Z1) Z1[o] = z;
+    H1[o] = (__bf16)gelu_f(z);
+}
+
+// softmax over the 3 logits (columns 0..2 of a 64-wide fp32 row) + b5;
+// with targets: per-row loss into loss_rows, dlogits (p - y)/B into a 64-wide
+// bf16 row (zeros beyond 3) and fp32 [rows][3]
+__global__ void softmax_ce_kernel(SoftmaxArgs a)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (r >= a.rows_pad) return;
+    const float* P = a.params + (size_t)m * a.pstride;
+    const float* lg = a.logits + ((size_t)m * a.rows_pad + r) * kPadOut;
+    float l[3];
+    for (int c = 0; c < 3; ++c) l[c] = lg[c] + P[kOffB5 + c];
+    const float mx = fmaxf(l[0], fmaxf(l[1], l[2]));
+    float e[3], s = 0.f;
+    for (int c = 0; c < 3; ++c) { e[c] = __expf(l[c] - mx); s += e[c]; }
+    const float is = 1.0f / s;
+    float p[3];
+    for (int c = 0; c < 3; ++c) p[c] = e[c] * is;
+    float* po = a.probs + ((size_t)m * a.rows_pad + r) * 3;
+    for (int c = 0; c < 3; ++c) po[c] = p[c];
+    if (a.ys) {
+        const float* y = a.ys + ((size_t)m * a.rows_pad + r) * 3;
+        const bool valid = r < a.rows;
+        const float ls = logf(s) + mx;
+        float loss = 0.f;
+        for (int c = 0; c < 3; ++c) loss -= y[c] * (l[c] - ls);
+        a.loss_rows[(size_t)m * a.rows_pad + r] = valid ? loss : 0.f;
+        __bf16* d = a.dlog + ((size_t)m * a.rows_pad + r) * kPadOut;
+        float* df = a.dlog_f + ((size_t)m * a.rows_pad + r) * 3;
+        for (int c = 0; c < 3; ++c) {
+            const float v = valid ? (p[c] - y[c]) * a.inv_batch : 0.f;
+            d[c] = (__bf16)v;
+            df[c] = v;
+        }
+        for (int c = 3; c < kPadOut; ++c) d[c] = (__bf16)0.0f;
+    }
+}
+
+// column sums of a [rows][cols] fp32 matrix per member, deterministic two
+// stages: partial[m][chunk][col] then out[m][col] (+= offset into grads)
+__global__ void colsum_partial_kernel(const float* src, int rows, int cols, size_t sstride, int chunk_rows,
+                                      float* partial)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch = blockIdx.y, m = blockIdx.z;
+    if (col >= cols) return;
+    const float* s = src + (size_t)m * sstride;
+    const int r0 = ch * chunk_rows;
+    const int r1 = r0 + chunk_rows < rows ? r0 + chunk_rows : rows;
+    float acc = 0.f;
+    for (int r = r0; r < r1; ++r) acc += s[(size_t)r * cols + col];
+    partial[((size_t)m * gridDim.y + ch) * cols + col] = acc;
+}
+
+__global__ void colsum_final_kernel(const float* partial, int chunks, int cols, float* out, size_t ostride)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (col >= cols) return;
+    float acc = 0.f;
+    for (int c = 0; c < chunks; ++c) acc += partial[((size_t)m * chunks + c) * cols + col];
+    out[(size_t)m * ostride + col] = acc;
+}
+
+// copy a [rows][cols] sub-block of a padded fp32 matrix into the flat gradient
+__global__ void copy_block_kernel(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
+                                  size_t dstride)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (idx >= rows * cols) return;
+    const int r = idx / cols, c = idx % cols;
+    dst[(size_t)m * dstride + idx] = src[(size_t)m * sstride + (size_t)r * src_ld + c];
+}
+
+// Adam on the flat fp32 parameters of every member, then the bf16 copies:
+// W2..W4 [256][256] and the two padded copies of W5.
+__global__ void adam_kernel(AdamArgs a)
+{
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= (size_t)kParams) return;
+    const size_t o = (size_t)m * kParams + j;
+    const float g = a.grads[o];
+    const float mm = a.b1 * a.m[o] + (1.0f - a.b1) * g;
+    const float vv = a.b2 * a.v[o] + (1.0f - a.b2) * g * g;
+    a.m[o] = mm;
+    a.v[o] = vv;
+    const float mh = mm * a.c1, vh = vv * a.c2;
+    const float w = a.w[o] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.w[o] = w;
+    if (j >= kOffW2 && j < kOffB2) a.wb[(size_t)m * kBfParams + kBfW2 + (j - kOffW2)] = (__bf16)w;
+    else if (j >= kOffW3 && j < kOffB3) a.wb[(size_t)m * kBfParams + kBfW3 + (j - kOffW3)] = (__bf16)w;
+    else if (j >= kOffW4 && j < kOffB4) a.wb[(size_t)m * kBfParams + kBfW4 + (j - kOffW4)] = (__bf16)w;
+    else if (j >= kOffW5 && j < kOffB5) {
+        const int k = (int)((j - kOffW5) / 3), c = (int)((j - kOffW5) % 3);
+        a.wb[(size_t)m * kBfParams + kBfW5p + (size_t)k * kPadOut + c] = (__bf16)w;
+        a.wb[(size_t)m * kBfParams + kBfW5t + (size_t)k * kPadK5 + c] = (__bf16)w;
+    }
+}
+
+// bf16 copies from the fp32 master weights (after loading a model)
+__global__ void refresh_bf16_kernel(const float* w, __bf16* wb)
+{
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (j >= (size_t)kBfParams) return;
+    const float* P = w + (size_t)m * kParams;
+    float v = 0.0f;
+    if (j < kBfW3) v = P[kOffW2 + (j - kBfW2)];
+    else if (j < kBfW4) v = P[kOffW3 + (j - kBfW3)];
+    else if (j < kBfW5p) v = P[kOffW4 + (j - kBfW4)];
+    else if (j < kBfW5t) {
+        const size_t k = (j - kBfW5p) / kPadOut, c = (j - kBfW5p) % kPadOut;
+        v = c < 3 ? P[kOffW5 + k * 3 + c] : 0.0f;
+    } else {
+        const size_t k = (j - kBfW5t) / kPadK5, c = (j - kBfW5t) % kPadK5;
+        v = c < 3 ? P[kOffW5 + k * 3 + c] : 0.0f;
+    }
+    wb[(size_t)m * kBfParams + j] = (__bf16)v;
+}
+
+__global__ void accumulate_kernel(const float* src, float* dst, int n, float scale)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += scale * src[i];
+}
+
+// member mean, spread = max_c (max_m p - min_m p), domain test of the raw
+// features against the training box, and the fallback decision
+__global__ void ensemble_gate_kernel(GateArgs a)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.rows) return;
+    float mean[3] = {0.f, 0.f, 0.f}, spread = 0.f;
+    for (int c = 0; c < 3; ++c) {
+        float lo = 1e30f, hi = -1e30f, s = 0.f;
+        for (int m = 0; m < a.nets; ++m) {
+            const float p = a.probs[((size_t)m * a.rows_pad + r) * 3 + c];
+            lo = fminf(lo, p); hi = fmaxf(hi, p); s += p;
+        }
+        mean[c] = s / (float)a.nets;
+        spread = fmaxf(spread, hi - lo);
+    }
+    const float* x = a.x + (size_t)r * kFeatures;
+    bool in = a.eligible ? a.eligible[r] != 0 : true;
+    for (int k = 0; k < kFeatures; ++k) in = in && x[k] >= a.lo[k] && x[k] <= a.hi[k];
+    const size_t o = (size_t)a.out_offset + r;
+    if (a.rat)
+        for (int c = 0; c < 3; ++c) a.rat[o * 3 + c] = mean[c];
+    if (a.spread) a.spread[o] = spread;
+    if (a.in_domain) a.in_domain[o] = in ? 1 : 0;
+    if (a.members)
+        for (int m = 0; m < a.nets; ++m)
+            for (int c = 0; c < 3; ++c)
+                a.members[((size_t)m * a.n_total + o) * 3 + c] = a.probs[((size_t)m * a.rows_pad + r) * 3 + c];
+}
+
+// per-feature mean, 1/std and min/max of n raw rows (one block, 8 x 128 threads)
+__global__ void feature_stats_kernel(const float* x, int64_t n, float* stats)
+{
+    __shared__ double s1[kFeatures][128], s2[kFeatures][128];
+    __shared__ float mn[kFeatures][128], mx[kFeatures][128];
+    const int k = threadIdx.y, t = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    float lo = 3e38f, hi = -3e38f;
+    for (int64_t i = t; i < n; i += 128) {
+        const float v = x[(size_t)i * kFeatures + k];
+        a += v; b += (double)v * v;
+        lo = fminf(lo, v); hi = fmaxf(hi, v);
+    }
+    s1[k][t] = a; s2[k][t] = b; mn[k][t] = lo; mx[k][t] = hi;
+    __syncthreads();
+    if (t == 0) {
+        double A = 0.0, Bq = 0.0;
+        float L = 3e38f, H = -3e38f;
+        for (int j = 0; j < 128; ++j) { A += s1[k][j]; Bq += s2[k][j]; L = fminf(L, mn[k][j]); H = fmaxf(H, mx[k][j]); }
+        const double mean = A / (double)n;
+        double var = Bq / (double)n - mean * mean;
+        if (var < 0) var = 0;
+        const double sd = sqrt(var);
+        stats[k] = (float)mean;
+        stats[kFeatures + k] = sd > 1e-6 ? (float)(1.0 / sd) : 1.0f;
+        stats[2 * kFeatures + k] = L;
+        stats[3 * kFeatures + k] = H;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sweep: fallback selection and compaction (count / scan / write), gather of
+// the fallback sub-problem, scatter of its Monte Carlo fractions, spectral
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool fallback_of(const SweepSelectArgs& a, int64_t i)
+{
+    return !(a.in_domain[i] != 0) || !(a.spread[i] <= a.spread_max);
+}
+
+__global__ void select_count_kernel(SweepSelectArgs a)
+{
+    __shared__ unsigned int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * kSelectPerBlock;
+    unsigned int c = 0;
+    for (int j = 0; j < 8; ++j) {
+        const int64_t i = b0 + (int64_t)threadIdx.x * 8 + j;
+        if (i < a.n) {
+            const bool f = fallback_of(a, i);
+            a.used_mc[i] = f ? 1 : 0;
+            c += f ? 1u : 0u;
+        }
+    }
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_count[blockIdx.x] = cnt;
+}
+
+__global__ __launch_bounds__(1024) void select_scan_kernel(unsigned long long* count, unsigned long long* offset,
+                                                           int blocks, unsigned long long* total)
+{
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (blocks + 1023) / 1024;
+    const int b = t * per, e = b + per < blocks ? b + per : blocks;
+    unsigned long long s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = t > 0 ? part[t - 1] : 0ull;
+    for (int i = b; i < e; ++i) { offset[i] = run; run += count[i]; }
+    if (t == 1023) *total = part[1023];
+}
+
+__global__ void select_write_kernel(SweepSelectArgs a)
+{
+    __shared__ unsigned int pre[256];
+    const int64_t b0 = (int64_t)blockIdx.x * kSelectPerBlock;
+    const int t = threadIdx.x;
+    unsigned int c = 0;
+    for (int j = 0; j < 8; ++j) {
+        const int64_t i = b0 + (int64_t)t * 8 + j;
+        if (i < a.n && a.used_mc[i]) ++c;
+    }
+    pre[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned int v = t >= off ? pre[t - off] : 0u;
+        __syncthreads();
+        pre[t] += v;
+        __syncthreads();
+    }
+    unsigned long long o = a.block_offset[blockIdx.x] + (t > 0 ? pre[t - 1] : 0u);
+    for (int j = 0; j < 8; ++j) {
+        const int64_t i = b0 + (int64_t)t * 8 + j;
+        if (i < a.n && a.used_mc[i]) a.idx[o++] = i;
+    }
+}
+
+__global__ void gather_items_kernel(GatherArgs a)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const int64_t i = a.idx[k];
+    a.o_n_layers[k] = a.n_layers[i];
+    for (int l = 0; l < a.L; ++l) {
+        const size_t s = (size_t)i * a.L + l, d = (size_t)k * a.L + l;
+        a.o_mu_s[d] = a.mu_s[s]; a.o_mu_a[d] = a.mu_a[s]; a.o_g[d] = a.g[s];
+        a.o_n_layer[d] = a.n_layer[s]; a.o_thickness[d] = a.thickness[s];
+    }
+    a.o_n_upper[k] = a.n_upper[i]; a.o_n_lower[k] = a.n_lower[i]; a.o_k_lower[k] = a.k_lower[i];
+    a.o_mu0[k] = a.mu0[i];
+    a.o_photons[k] = a.photons;
+}
+
+// R = (specular + diffuse)/N, A, T of fallback item k into row idx[k]
+__global__ void scatter_mc_kernel(int64_t m, const int64_t* idx, const unsigned long long* t, float* rat)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const unsigned long long* tk = t + (size_t)k * 6;
+    const double N = (double)(tk[0] + tk[1] + tk[2] + tk[3] + tk[4]);
+    const int64_t i = idx[k];
+    rat[i * 3 + 0] = (float)((double)(tk[0] + tk[1]) / N);
+    rat[i * 3 + 1] = (float)((double)tk[2] / N);
+    rat[i * 3 + 2] = (float)((double)tk[3] / N);
+}
+
+// out[d] = (sum_l w_r[l] R[d][l], sum_l w_e[l] A[d][l]) -- one wave per design
+__global__ void spectral_reduce_kernel(int designs, int lambdas, const float* rat, const float* w_r, const float* w_e,
+                                       float* out)
+{
+    const int d = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (d >= designs) return;
+    float r = 0.f, e = 0.f;
+    for (int l = lane; l < lambdas; l += 64) {
+        const float* p = rat + ((size_t)d * lambdas + l) * 3;
+        r = fmaf(w_r[l], p[0], r);
+        e = fmaf(w_e[l], p[1], e);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        r += __shfl_xor(r, off);
+        e += __shfl_xor(e, off);
+    }
+    if (lane == 0) { out[2 * (size_t)d] = r; out[2 * (size_t)d + 1] = e; }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_select_count(const SweepSelectArgs& a, hipStream_t st)
+{
+    const int64_t blocks = (a.n + kSelectPerBlock - 1) / kSelectPerBlock;
+    hipLaunchKernelGGL(select_count_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_scan(const SweepSelectArgs& a, unsigned long long* total, hipStream_t st)
+{
+    const int blocks = (int)((a.n + kSelectPerBlock - 1) / kSelectPerBlock);
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(1024), 0, st, a.block_count, a.block_offset, blocks, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_write(const SweepSelectArgs& a, hipStream_t st)
+{
+    const int64_t blocks = (a.n + kSelectPerBlock - 1) / kSelectPerBlock;
+    hipLaunchKernelGGL(select_write_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_items(const GatherArgs& a, hipStream_t st)
+{
+    if (a.m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_items_kernel, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_mc(int64_t m, const int64_t* idx, const unsigned long long* tallies, float* rat,
+                             hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_mc_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, idx, tallies, rat);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectral_reduce(int designs, int lambdas, const float* rat, const float* w_r, const float* w_e,
+                                  float* out, hipStream_t st)
+{
+    if (designs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(spectral_reduce_kernel, dim3((designs + 3) / 4), dim3(256), 0, st, designs, lambdas, rat, w_r,
+                       w_e, out);
+    return hipGetLastError();
+}
+hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
+                           const float* g, const float* n_layer, const float* thickness, const float* n_upper,
+                           const float* n_lower, const float* k_lower, const float* mu0, float* x,
+                           uint8_t* eligible, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(features_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, L, n_layers, mu_s, mu_a, g,
+                       n_layer, thickness, n_upper, n_lower, k_lower, mu0, x, eligible);
+    return hipGetLastError();
+}
+
+hipError_t launch_standardize(const StdArgs& a, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(standardize_kernel, dim3((a.rows_pad + 255) / 256, nets), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_layer(int rows_pad, const float* xs, const float* params, size_t pstride, float* Z1,
+                              __bf16* H1, int nets, hipStream_t st)
+{
+    const size_t tot = (size_t)rows_pad * kHidden;
+    hipLaunchKernelGGL(first_layer_kernel, dim3((unsigned)((tot + 255) / 256), nets), dim3(256), 0, st, rows_pad,
+                       xs, params, pstride, Z1, H1);
+    return hipGetLastError();
+}
+
+hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(softmax_ce_kernel, dim3((a.rows_pad + 255) / 256, nets), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* src, int rows, int cols, size_t sstride, float* partial, int chunks,
+                         float* out, size_t ostride, int nets, hipStream_t st)
+{
+    const int chunk_rows = (rows + chunks - 1) / chunks;
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((cols + 63) / 64, chunks, nets), dim3(64), 0, st, src, rows,
+                       cols, sstride, chunk_rows, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 63) / 64, nets), dim3(64), 0, st, partial, chunks, cols,
+                       out, ostride);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
+                             size_t dstride, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(copy_block_kernel, dim3((rows * cols + 255) / 256, nets), dim3(256), 0, st, src, src_ld,
+                       sstride, rows, cols, dst, dstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256, nets), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(refresh_bf16_kernel, dim3((unsigned)((kBfParams + 255) / 256), nets), dim3(256), 0, st, w, wb);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st)
+{
+    hipLaunchKernelGGL(accumulate_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_ensemble_gate(const GateArgs& a, hipStream_t st)
+{
+    if (a.rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ensemble_gate_kernel, dim3((a.rows + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_feature_stats(const float* x, int64_t n, float* stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(feature_stats_kernel, dim3(1), dim3(128, kFeatures), 0, st, x, n, stats);
+    return hipGetLastError();
+}
+
+}  // namespace fos

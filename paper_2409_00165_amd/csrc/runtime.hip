@@ -12,68 +12,14 @@
 #include "fos_device.hpp"
 #include "fos_kernels.hpp"
 #include "fos_mc.h"
+#include "fos_ctx.hpp"
 
-struct fos_ctx {
-    int device = 0;
-    int n_cu = 0;
-    std::string err;
-    // prepared problem
-    int32_t n_items = 0, max_layers = 0;
-    bool prepared = false;
-    float4* table = nullptr;
-    size_t table_bytes = 0;
-    unsigned long long* chunk_prefix = nullptr;    // [n_items + 1]
-    size_t chunk_prefix_bytes = 0;
-    unsigned long long* chunk_counter = nullptr;   // device, 1 word
-    unsigned long long* err_dev = nullptr;   // device, 1 word
-    unsigned long long* err_host = nullptr;  // pinned host, 1 word
-    fos_mc_launch defaults{};
-    // optics scratch
-    int* cell_of = nullptr;
-    size_t cell_of_bytes = 0;
-    double* mie = nullptr;
-    size_t mie_bytes = 0;
-    double2* mie_scratch = nullptr;
-    size_t mie_scratch_bytes = 0;
-    unsigned int* nmax_dev = nullptr;        // device, 1 word
-    unsigned long long* aux_host = nullptr;  // pinned host, 4 words
-    // tuning and graph
-    unsigned long long* tune_tallies = nullptr;
-    size_t tune_tallies_bytes = 0;
-    unsigned long long* seed_dev = nullptr;  // device, 1 word
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    hipStream_t capture_stream = nullptr;
-    uint64_t prepare_epoch = 0, graph_epoch = 0;
-};
+using fosrt::DeviceGuard;
+using fosrt::fail;
+using fosrt::grow;
+using fosrt::hip_fail;
 
 namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-fos_status fail(fos_ctx* c, fos_status s, const std::string& msg)
-{
-    if (c) c->err = msg;
-    return s;
-}
-
-fos_status hip_fail(fos_ctx* c, hipError_t e, const char* what)
-{
-    if (e == hipErrorOutOfMemory)
-        return fail(c, FOS_E_OUT_OF_MEMORY, std::string(what) + ": out of device memory");
-    return fail(c, FOS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
 
 const char* field_name(int code)
 {
@@ -118,21 +64,6 @@ fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
     return r;
 }
 
-template <class T>
-hipError_t grow(T*& p, size_t& cap, size_t need_bytes)
-{
-    if (need_bytes <= cap && p) return hipSuccess;
-    if (p) {
-        hipError_t e = hipFree(p);
-        p = nullptr;
-        cap = 0;
-        if (e != hipSuccess) return e;
-    }
-    size_t want = std::max<size_t>(need_bytes, 256);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), want);
-    if (e == hipSuccess) cap = want;
-    return e;
-}
 
 }  // namespace
 
@@ -207,6 +138,7 @@ void fos_destroy(fos_ctx* c)
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+        fos_sur_free(c->sur);
     }
     delete c;
 }
@@ -446,6 +378,18 @@ fos_status fos_mc_graph_launch(fos_ctx* c, uint64_t seed, void* hip_stream)
     hipError_t e = fos::launch_fill_u64(c->seed_dev, (unsigned long long)seed, 1, st);
     if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, st);
     return e == hipSuccess ? FOS_OK : hip_fail(c, e, "graph launch");
+}
+
+fos_status fos_mc_fractions(fos_ctx* c, int32_t n, const uint64_t* tallies, float* rat, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (n < 0) return fail(c, FOS_E_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!tallies || !rat)) return fail(c, FOS_E_INVALID_ARG, "NULL array");
+    DeviceGuard g(c->device);
+    hipError_t e = fos::launch_fractions(n, reinterpret_cast<const unsigned long long*>(tallies), rat,
+                                         reinterpret_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? FOS_OK : hip_fail(c, e, "fractions kernel");
 }
 
 fos_status fos_mc_run(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const fos_mc_launch* launch,

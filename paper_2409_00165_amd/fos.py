@@ -42,6 +42,11 @@ class fos_optics_problem(Structure):
                 ("f", c_void_p)]
 
 
+class fos_train_opts(Structure):
+    _fields_ = [("epochs", c_int32), ("batch", c_int32), ("lr", c_float), ("lr_min", c_float),
+                ("seed", c_uint64), ("resume", c_int32), ("loss_history", c_void_p)]
+
+
 class fos_mc_launch(Structure):
     _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
                 ("blocks_per_cu", c_int32), ("max_steps", c_uint64)]
@@ -90,6 +95,26 @@ def lib():
         L.fos_mc_graph_capture.restype = c_int
         L.fos_mc_graph_launch.argtypes = [c_void_p, c_uint64, c_void_p]
         L.fos_mc_graph_launch.restype = c_int
+        L.fos_sur_features.argtypes = [c_void_p, POINTER(fos_mc_problem), c_void_p, c_void_p, c_void_p]
+        L.fos_sur_features.restype = c_int
+        L.fos_sur_train.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int64, POINTER(fos_train_opts), c_void_p]
+        L.fos_sur_train.restype = c_int
+        L.fos_sur_predict.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p]
+        L.fos_sur_predict.restype = c_int
+        L.fos_sur_grad.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p]
+        L.fos_sur_grad.restype = c_int
+        L.fos_sur_save.argtypes = [c_void_p, c_void_p, POINTER(ctypes.c_size_t)]
+        L.fos_sur_save.restype = c_int
+        L.fos_sur_load.argtypes = [c_void_p, c_void_p, ctypes.c_size_t]
+        L.fos_sur_load.restype = c_int
+        L.fos_mc_fractions.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+        L.fos_mc_fractions.restype = c_int
+        L.fos_sweep_run.argtypes = [c_void_p, POINTER(fos_mc_problem), c_float, c_uint64, c_uint64, c_void_p,
+                                    c_void_p, c_void_p, POINTER(ctypes.c_int64), c_void_p]
+        L.fos_sweep_run.restype = c_int
+        L.fos_spectral_reduce.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fos_spectral_reduce.restype = c_int
         L.fos_optics_run.argtypes = [c_void_p, POINTER(fos_optics_problem), c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]
         L.fos_optics_run.restype = c_int
@@ -253,6 +278,12 @@ def fos_mc_graph_launch(ctx, seed: int, stream=None) -> None:
     _check(ctx, lib().fos_mc_graph_launch(ctx, c_uint64(seed), _stream(stream)))
 
 
+def fos_mc_fractions(ctx, tallies, rat, stream=None) -> None:
+    import torch
+    n = tallies.numel() // N_TALLY
+    _check(ctx, lib().fos_mc_fractions(ctx, n, _ptr(tallies), _ptr(rat, torch.float32, 3 * n), _stream(stream)))
+
+
 def fos_mc_prepared_items(ctx) -> int:
     return lib().fos_mc_prepared_items(ctx)
 
@@ -301,6 +332,89 @@ def fos_optics_run(ctx, problem: OpticsProblem, mu_s=None, mu_a=None, g=None, ou
                                      _ptr(mu_s, torch.float32, C), _ptr(mu_a, torch.float32, C),
                                      _ptr(g, torch.float32, C), _ptr(out_f64, torch.float64, 3 * C),
                                      _stream(stream)))
+
+
+SUR_FEATURES = 8
+SUR_MEMBERS = 4
+SUR_PARAMS = 200451
+
+
+def fos_sur_features(ctx, problem: MCProblem, x, eligible=None, stream=None) -> None:
+    import torch
+    n = problem.n_items
+    _check(ctx, lib().fos_sur_features(ctx, ctypes.byref(problem.struct), _ptr(x, torch.float32, n * SUR_FEATURES),
+                                       _ptr(eligible, torch.uint8, n), _stream(stream)))
+
+
+def fos_sur_train(ctx, x, y, epochs=10, batch=8192, lr=1e-3, lr_min=1e-5, seed=1, resume=False,
+                  loss_history=None, stream=None) -> None:
+    import torch
+    n = x.numel() // SUR_FEATURES
+    o = fos_train_opts(epochs, batch, lr, lr_min, seed, 1 if resume else 0,
+                       _ptr(loss_history, torch.float32, epochs * SUR_MEMBERS))
+    _check(ctx, lib().fos_sur_train(ctx, _ptr(x, torch.float32, n * SUR_FEATURES), _ptr(y, torch.float32, n * 3),
+                                    n, ctypes.byref(o), _stream(stream)))
+
+
+def fos_sur_predict(ctx, x, eligible=None, rat=None, spread=None, in_domain=None, members=None,
+                    stream=None) -> None:
+    import torch
+    n = x.numel() // SUR_FEATURES
+    _check(ctx, lib().fos_sur_predict(ctx, _ptr(x, torch.float32, n * SUR_FEATURES), _ptr(eligible, torch.uint8, n),
+                                      n, _ptr(rat, torch.float32, 3 * n), _ptr(spread, torch.float32, n),
+                                      _ptr(in_domain, torch.uint8, n),
+                                      _ptr(members, torch.float32, SUR_MEMBERS * 3 * n), _stream(stream)))
+
+
+def fos_sur_grad(ctx, x, y, grads, loss=None, stream=None) -> None:
+    import torch
+    n = x.numel() // SUR_FEATURES
+    _check(ctx, lib().fos_sur_grad(ctx, _ptr(x, torch.float32), _ptr(y, torch.float32, 3 * n), n,
+                                   _ptr(grads, torch.float32, SUR_MEMBERS * SUR_PARAMS),
+                                   _ptr(loss, torch.float32, SUR_MEMBERS), _stream(stream)))
+
+
+def fos_sur_save(ctx) -> bytes:
+    n = ctypes.c_size_t(0)
+    _check(ctx, lib().fos_sur_save(ctx, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(ctx, lib().fos_sur_save(ctx, buf, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def fos_sur_load(ctx, blob: bytes) -> None:
+    _check(ctx, lib().fos_sur_load(ctx, blob, len(blob)))
+
+
+def fos_sweep_run(ctx, problem: MCProblem, spread_max: float, fallback_photons: int, seed: int, rat, used_mc,
+                  spread=None, stream=None) -> int:
+    """Surrogate + Monte Carlo fallback for every item; returns the number of
+    items that went to Monte Carlo."""
+    import torch
+    n = problem.n_items
+    nf = ctypes.c_int64(0)
+    _check(ctx, lib().fos_sweep_run(ctx, ctypes.byref(problem.struct), c_float(spread_max), c_uint64(fallback_photons),
+                                    c_uint64(seed), _ptr(rat, torch.float32, 3 * n), _ptr(spread, torch.float32, n),
+                                    _ptr(used_mc, torch.uint8, n), ctypes.byref(nf), _stream(stream)))
+    return nf.value
+
+
+def fos_spectral_reduce(ctx, designs: int, lambdas: int, rat, w_r, w_e, out, stream=None) -> None:
+    import torch
+    _check(ctx, lib().fos_spectral_reduce(ctx, designs, lambdas, _ptr(rat, torch.float32, designs * lambdas * 3),
+                                          _ptr(w_r, torch.float32, lambdas), _ptr(w_e, torch.float32, lambdas),
+                                          _ptr(out, torch.float32, 2 * designs), _stream(stream)))
+
+
+def parse_sur_blob(blob: bytes):
+    """(stats [4, 8], params [4, SUR_PARAMS], adam_step) of a fos_sur_save blob."""
+    import numpy as np
+    assert blob[:8] == b"FOSSUR01"
+    hdr = np.frombuffer(blob[8:32], np.uint32)
+    stats = np.frombuffer(blob[32:160], np.float32).reshape(4, 8)
+    P = int(hdr[0]) * int(hdr[3])
+    params = np.frombuffer(blob[160:160 + 4 * P], np.float32).reshape(int(hdr[0]), int(hdr[3]))
+    return stats, params, int(hdr[5])
 
 
 def fos_philox_words(ctx, photon, step, stream_ids, seed: int, out, stream=None) -> None:

@@ -1,0 +1,116 @@
+"""Surrogate pipeline on one GPU: Monte Carlo labels -> ensemble training ->
+design sweep with Monte Carlo fallback.
+
+Every numerical step runs in libfos_mc (optics, walk, fractions, features,
+training, prediction, gate, compaction, reductions); this module only
+orchestrates the calls and moves device tensors around.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import fos
+from . import workloads as W
+
+
+def device_problem(arrays, device="cuda"):
+    """MCProblem from a dict of numpy arrays (item_geometry() layout plus
+    mu_s, mu_a, g)."""
+    I = len(arrays["n_layers"])
+    return fos.MCProblem.from_numpy(device, arrays["n_layers"], np.asarray(arrays["mu_s"]).reshape(I, -1),
+                                    np.asarray(arrays["mu_a"]).reshape(I, -1), np.asarray(arrays["g"]).reshape(I, -1),
+                                    np.asarray(arrays["n_layer"]).reshape(I, -1),
+                                    np.asarray(arrays["thickness"]).reshape(I, -1), arrays["n_upper"],
+                                    arrays["n_lower"], arrays["k_lower"], arrays["mu0"],
+                                    np.asarray(arrays["photons"]).astype(np.int64))
+
+
+def optics_problem(ctx, wl, device="cuda"):
+    """GPU effective-medium optics of a workload, then its transport problem."""
+    import torch
+    req = W.optics_request(wl)
+    op = fos.OpticsProblem.from_request(req, device)
+    C = op.n_cells
+    mus, mua, g = (torch.zeros(C, dtype=torch.float32, device=device) for _ in range(3))
+    fos.fos_optics_run(ctx, op, mus, mua, g)
+    geo = W.item_geometry(wl)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    ph = t(geo["photons"].astype(np.int64), np.int64)
+    if hasattr(torch, "uint64"):
+        ph = ph.view(torch.uint64)
+    return fos.MCProblem(t(geo["n_layers"], np.int32), mus, mua, g, t(geo["n_layer"], np.float32).reshape(-1),
+                         t(geo["thickness"], np.float32).reshape(-1), t(geo["n_upper"], np.float32),
+                         t(geo["n_lower"], np.float32), t(geo["k_lower"], np.float32), t(geo["mu0"], np.float32), ph)
+
+
+def with_photons(prob, photons: int):
+    """The same problem with every item's photon budget replaced."""
+    import torch
+    T = dict(prob.tensors)
+    ph = torch.full((prob.n_items,), photons, dtype=torch.int64, device=T["photons"].device)
+    if hasattr(torch, "uint64"):
+        ph = ph.view(torch.uint64)
+    T["photons"] = ph
+    return fos.MCProblem(**T)
+
+
+def mc_fractions(ctx, prob, seed: int):
+    """Run the walk on every item; returns (rat [n*3] device, photon-steps)."""
+    import torch
+    n = prob.n_items
+    tal = torch.zeros(n * fos.N_TALLY, dtype=torch.int64, device="cuda")
+    fos.fos_mc_run(ctx, prob, seed, tal)
+    rat = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
+    fos.fos_mc_fractions(ctx, tal, rat)
+    steps = int(tal.view(n, fos.N_TALLY)[:, 5].sum().item())
+    return rat, steps
+
+
+def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000, log=None):
+    """n single-layer items labelled by the walk at `photons` each.
+    Returns (x [n*8], y [n*3], photon-steps, seconds)."""
+    import torch
+    xs, ys = [], []
+    steps = 0
+    t0 = time.perf_counter()
+    for c, b in enumerate(range(0, n, chunk)):
+        m = min(chunk, n - b)
+        arrays = W.surrogate_training_items(m, seed + 7919 * c, photons=photons)
+        prob = device_problem(arrays)
+        x = torch.zeros(m * fos.SUR_FEATURES, dtype=torch.float32, device="cuda")
+        fos.fos_sur_features(ctx, prob, x)
+        rat, s = mc_fractions(ctx, prob, seed + c)
+        xs.append(x)
+        ys.append(rat)
+        steps += s
+        if log:
+            log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
+    torch.cuda.synchronize()
+    return torch.cat(xs), torch.cat(ys), steps, time.perf_counter() - t0
+
+
+def train(ctx, x, y, epochs=30, batch=8192, lr=1e-3, lr_min=1e-5, seed=1):
+    import torch
+    hist = torch.zeros(epochs * fos.SUR_MEMBERS, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    fos.fos_sur_train(ctx, x, y, epochs=epochs, batch=batch, lr=lr, lr_min=lr_min, seed=seed, loss_history=hist)
+    torch.cuda.synchronize()
+    return hist.cpu().numpy().reshape(epochs, fos.SUR_MEMBERS), time.perf_counter() - t0
+
+
+def predict(ctx, x):
+    import torch
+    n = x.numel() // fos.SUR_FEATURES
+    rat = torch.zeros(n * 3, device="cuda")
+    spread = torch.zeros(n, device="cuda")
+    ind = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fos.fos_sur_predict(ctx, x, rat=rat, spread=spread, in_domain=ind)
+    return rat, spread, ind
+
+
+def errors(a, b):
+    """max, mean and 99th percentile of |a - b| (flattened)."""
+    d = np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).ravel()
+    return {"max": float(d.max()), "mean": float(d.mean()), "p99": float(np.quantile(d, 0.99))}

@@ -309,3 +309,54 @@ def optics_request(wl: Workload):
         n_p[idx] = npl; k_p[idx] = kpl; r[idx] = rl; f[idx] = fl
     return {"lam": lam, "n_m": n_m, "k_m": k_m, "offsets": offsets,
             "n_p": n_p, "k_p": k_p, "r": r, "f": f, "cells": C, "max_layers": L}
+
+
+# ----------------------------------------------------------------------------
+# surrogate training set and sweep weights (inputs only)
+# ----------------------------------------------------------------------------
+
+# Box of the training inputs, covering the optical depths and asymmetries of
+# the two-species and three-layer workloads (their optics span tau_s 1e-8 ..
+# 3.2e3, tau_a 5e-4 .. 1.2e2, g 0 .. 0.995).
+TRAIN_TAU_S = (1e-7, 5e3)
+TRAIN_TAU_A = (1e-4, 3e2)
+TRAIN_G = (0.0, 0.999)
+
+
+def surrogate_training_items(n: int, seed: int, photons: int = 100_000, thickness: float = 100.0):
+    """Single-layer items for Monte Carlo labels: tau_s and tau_a log-uniform
+    over the box above, g uniform, matrix n ~ U[1.3, 1.7], substrate n ~
+    U[1, 3.5] (a quarter exactly 1, air), k ~ 0 for half else log-U[1e-3,
+    1e-1], incidence cosine ~ U[0.5, 1] (a quarter exactly 1), air above.
+    Returns numpy arrays shaped like item_geometry() plus mu_s, mu_a, g."""
+    rng = np.random.default_rng(seed)
+    lu = lambda lo, hi: np.exp(rng.uniform(math.log(lo), math.log(hi), n))
+    tau_s = lu(*TRAIN_TAU_S)
+    tau_a = lu(*TRAIN_TAU_A)
+    g = rng.uniform(*TRAIN_G, n)
+    n_m = rng.uniform(1.3, 1.7, n)
+    n_sub = np.where(rng.uniform(size=n) < 0.25, 1.0, rng.uniform(1.0, 3.5, n))
+    k_sub = np.where(rng.uniform(size=n) < 0.5, 0.0, lu(1e-3, 1e-1))
+    mu0 = np.where(rng.uniform(size=n) < 0.25, 1.0, rng.uniform(0.5, 1.0, n))
+    t = np.full(n, thickness)
+    return {"n_layers": np.ones(n, np.int32), "mu_s": (tau_s / t)[:, None], "mu_a": (tau_a / t)[:, None],
+            "g": g[:, None], "n_layer": n_m[:, None], "thickness": t[:, None], "n_upper": np.ones(n),
+            "n_lower": n_sub, "k_lower": k_sub, "mu0": mu0, "photons": np.full(n, photons, np.uint64)}
+
+
+def planck_weights(lam: np.ndarray, temperature: float, lo: float, hi: float) -> np.ndarray:
+    """Normalised trapezoid weights of a blackbody spectrum (Planck's law at
+    `temperature` K) over [lo, hi] um on the wavelength grid -- the stand-in
+    for a measured solar spectrum (5778 K) or for the thermal emission band
+    (300 K); weights outside the band are zero."""
+    lam = np.asarray(lam, np.float64)
+    c2 = 14387.769  # um K
+    B = 1.0 / (lam**5 * (np.exp(c2 / (lam * temperature)) - 1.0))
+    inside = (lam >= lo) & (lam <= hi)
+    w = np.zeros_like(lam)
+    idx = np.nonzero(inside)[0]
+    for a, b in zip(idx[:-1], idx[1:]):
+        h = lam[b] - lam[a]
+        w[a] += 0.5 * h * B[a]
+        w[b] += 0.5 * h * B[b]
+    return w / w.sum()

@@ -1,0 +1,118 @@
+"""Surrogate + Monte Carlo fallback sweep (fos_sweep_run) and reductions."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def trained(torch):
+    """A small ensemble trained on 32768 walk-labelled items (1e4 photons)."""
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    c = fos.Context(0)
+    x, y, steps, secs = SP.make_training_set(c.handle, 32768, 10_000, seed=11, chunk=32768)
+    hist, _ = SP.train(c.handle, x, y, epochs=8, batch=2048, lr=2e-3, lr_min=1e-4, seed=2)
+    print("small training: loss by epoch", hist.mean(1), flush=True)
+    yield c
+    c.close()
+
+
+def _paint(n_designs=12, n_lambda=40):
+    from paper_2409_00165_amd import workloads as W
+    return W.paint_1layer(n_designs, n_lambda=n_lambda, photons=20_000)
+
+
+def test_sweep_all_fallback_equals_plain_monte_carlo(trained, torch):
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    h = trained.handle
+    prob = SP.optics_problem(h, _paint())
+    n = prob.n_items
+    rat = torch.zeros(3 * n, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    nf = fos.fos_sweep_run(h, prob, 0.0, 20_000, 77, rat, used)       # spread > 0 always -> all MC
+    ref, _ = SP.mc_fractions(h, SP.with_photons(prob, 20_000), 77)
+    torch.cuda.synchronize()
+    assert nf == n and bool((used == 1).all())
+    assert torch.equal(rat, ref)
+
+
+def test_sweep_without_fallback_equals_prediction(trained, torch):
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    h = trained.handle
+    prob = SP.optics_problem(h, _paint())
+    n = prob.n_items
+    x = torch.zeros(8 * n, device="cuda")
+    elig = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fos.fos_sur_features(h, prob, x, elig)
+    pr, sp, ind = SP.predict(h, x)
+    rat = torch.zeros(3 * n, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    spread = torch.zeros(n, device="cuda")
+    nf = fos.fos_sweep_run(h, prob, 1e9, 20_000, 77, rat, used, spread=spread)
+    torch.cuda.synchronize()
+    inside = ind.bool()
+    assert nf == int((~inside).sum().item())
+    assert torch.equal(used.bool(), ~inside)
+    assert torch.equal(rat.view(n, 3)[inside], pr.view(n, 3)[inside])
+    assert torch.equal(spread, sp)
+
+
+def test_multilayer_items_always_fall_back(trained, torch):
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    from paper_2409_00165_amd import workloads as W
+    h = trained.handle
+    prob = SP.optics_problem(h, W.stacks_3layer(n_designs=2, n_lambda=20, photons_lo=2e4, photons_hi=2e4))
+    n = prob.n_items
+    rat = torch.zeros(3 * n, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    nf = fos.fos_sweep_run(h, prob, 1e9, 20_000, 5, rat, used)
+    torch.cuda.synchronize()
+    assert nf == n
+    r = rat.view(n, 3).cpu().numpy()
+    assert np.allclose(r.sum(1), 1.0, atol=1e-5)
+
+
+def test_spectral_reduce_matches_host(trained, torch):
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    h = trained.handle
+    rng = np.random.default_rng(1)
+    D, L = 37, 200
+    rat = rng.dirichlet(np.ones(3), size=D * L).astype(np.float32)
+    lam = W.grid_log(0.3, 16.0, L)
+    wr = W.planck_weights(lam, 5778.0, 0.3, 2.5).astype(np.float32)
+    we = W.planck_weights(lam, 300.0, 8.0, 13.0).astype(np.float32)
+    assert abs(wr.sum() - 1) < 1e-6 and abs(we.sum() - 1) < 1e-6
+    out = torch.zeros(2 * D, device="cuda")
+    fos.fos_spectral_reduce(h, D, L, torch.from_numpy(rat.ravel()).cuda(), torch.from_numpy(wr).cuda(),
+                            torch.from_numpy(we).cuda(), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(D, 2)
+    r3 = rat.reshape(D, L, 3).astype(np.float64)
+    assert np.allclose(o[:, 0], r3[:, :, 0] @ wr, atol=1e-5)
+    assert np.allclose(o[:, 1], r3[:, :, 1] @ we, atol=1e-5)
+
+
+def test_trained_surrogate_tracks_monte_carlo(trained, torch):
+    """Held-out items drawn like the training set: the small ensemble is
+    within a loose bound of the walk (it is the machinery, not the accuracy,
+    under test here; the full-size accuracy is measured by the benchmark)."""
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    h = trained.handle
+    x, y, _, _ = SP.make_training_set(h, 4096, 10_000, seed=999, chunk=4096)
+    rat, spread, ind = SP.predict(h, x)
+    torch.cuda.synchronize()
+    e = SP.errors(rat.cpu().numpy(), y.cpu().numpy())
+    print("held-out error vs MC (small model):", e, "in-domain", float(ind.float().mean()), flush=True)
+    assert e["mean"] < 0.05

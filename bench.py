@@ -200,6 +200,148 @@ def sweep_main(args):
     return 0
 
 
+def surrogate_main(args):
+    """Surrogate pipeline: walk-labelled training set (single layers, inputs
+    log-uniform over the workloads' optical depths, `train_photons` each),
+    4-member ensemble training, then a paint-design sweep (`designs` x
+    `lambdas`, one layer in air) run two ways -- plain Monte Carlo at
+    `fallback_photons` and surrogate + Monte Carlo fallback -- both verified
+    against 1e6-photon Monte Carlo on the surrogate's top designs and on
+    random designs."""
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    from paper_2409_00165_amd import workloads as W
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    say("surrogate pipeline start")
+    rec_train = {}
+    if args.load_model:
+        fos.fos_sur_load(h, open(args.load_model, "rb").read())
+        say(f"model loaded from {args.load_model}")
+    else:
+        if args.load_data:
+            z = np.load(args.load_data)
+            x = torch.from_numpy(z["x"]).cuda()
+            y = torch.from_numpy(z["y"]).cuda()
+            rec_train = {"samples": int(len(z["y"]) // 3), "photons_each": int(z["photons"]),
+                         "labels": f"loaded from {os.path.basename(args.load_data)}"}
+            say(f"training set loaded: {rec_train['samples']} samples")
+        else:
+            x, y, steps, secs = SP.make_training_set(h, args.train_samples, args.train_photons, seed=20240931,
+                                                     log=say)
+            rec_train = {"samples": args.train_samples, "photons_each": args.train_photons, "label_seconds": secs,
+                         "label_photon_steps": steps, "label_photon_steps_per_s": steps / secs}
+        if args.save_data:
+            xh0, yh0, _, _ = SP.make_training_set(h, 10_000, args.train_photons, seed=777, chunk=10_000)
+            np.savez(args.save_data, x=x.cpu().numpy(), y=y.cpu().numpy(), xh=xh0.cpu().numpy(),
+                     yh=yh0.cpu().numpy(), photons=args.train_photons)
+            say(f"training and held-out sets written to {args.save_data}")
+        hist, tsec = SP.train(h, x, y, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_min=args.lr * 1e-2,
+                              seed=5)
+        rec_train.update({"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": tsec,
+                          "loss_first_epoch": hist[0].tolist(), "loss_last_epoch": hist[-1].tolist()})
+        say(f"trained {args.epochs} epochs in {tsec:.1f} s; mean loss {hist[0].mean():.4f} -> {hist[-1].mean():.4f}")
+        del x, y
+        if args.save_model:
+            open(args.save_model, "wb").write(fos.fos_sur_save(h))
+    # held-out set drawn like the training set
+    if args.load_data:
+        z = np.load(args.load_data)
+        xh, yh = torch.from_numpy(z["xh"]).cuda(), torch.from_numpy(z["yh"]).cuda()
+    else:
+        xh, yh, _, _ = SP.make_training_set(h, 10_000, args.train_photons, seed=777, chunk=10_000)
+    rh, sh, ih = SP.predict(h, xh)
+    torch.cuda.synchronize()
+    eh = SP.errors(rh.cpu().numpy(), yh.cpu().numpy())
+    spread_h = sh.cpu().numpy()
+    rec_held = {"n": 10_000, "error_vs_mc": eh, "frac_spread_gt_max": float((spread_h > args.spread_max).mean()),
+                "frac_in_domain": float(ih.float().mean().item())}
+    say(f"held-out error vs MC {eh}")
+
+    # the sweep
+    wl = W.paint_1layer(args.designs, n_lambda=args.lambdas, photons=args.fallback_photons)
+    prob = SP.optics_problem(h, wl)
+    n = prob.n_items
+    D, L = args.designs, args.lambdas
+    torch.cuda.synchronize()
+    say(f"sweep problem ready: {D} designs x {L} wavelengths")
+    t0 = time.perf_counter()
+    rat_mc, steps_mc = SP.mc_fractions(h, prob, 424242)
+    torch.cuda.synchronize()
+    t_mc = time.perf_counter() - t0
+    say(f"plain Monte Carlo sweep {t_mc:.2f} s")
+    rat_s = torch.zeros(3 * n, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    spread = torch.zeros(n, device="cuda")
+    fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515151, rat_s, used, spread=spread)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_fb = fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515152, rat_s, used, spread=spread)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    say(f"surrogate + fallback sweep {t_sur:.3f} s, {n_fb} of {n} items on Monte Carlo")
+    # reductions: solar-weighted R (5778 K Planck stand-in) and 8-13 um emittance
+    lam = wl.wavelengths
+    wr = torch.from_numpy(W.planck_weights(lam, 5778.0, 0.3, 2.5).astype(np.float32)).cuda()
+    we = torch.from_numpy(W.planck_weights(lam, 300.0, 8.0, 13.0).astype(np.float32)).cuda()
+    red_s = torch.zeros(2 * D, device="cuda")
+    red_m = torch.zeros(2 * D, device="cuda")
+    fos.fos_spectral_reduce(h, D, L, rat_s, wr, we, red_s)
+    fos.fos_spectral_reduce(h, D, L, rat_mc, wr, we, red_m)
+    fom = red_s.view(D, 2).sum(1).cpu().numpy()
+    K = min(args.verify_designs, D)
+    top = np.argsort(-fom)[:K]
+    rnd = np.random.default_rng(3).choice(D, size=K, replace=False)
+    ver = {}
+    for name, designs in (("top", top), ("random", rnd)):
+        items = (designs[:, None] * L + np.arange(L)[None, :]).ravel()
+        sub = {k: v for k, v in W.item_geometry(wl).items()}
+        T = prob.tensors
+        idx = torch.from_numpy(items).cuda()
+        sub_prob = fos.MCProblem(T["n_layers"][idx].contiguous(), T["mu_s"][idx].contiguous(),
+                                 T["mu_a"][idx].contiguous(), T["g"][idx].contiguous(),
+                                 T["n_layer"][idx].contiguous(), T["thickness"][idx].contiguous(),
+                                 T["n_upper"][idx].contiguous(), T["n_lower"][idx].contiguous(),
+                                 T["k_lower"][idx].contiguous(), T["mu0"][idx].contiguous(),
+                                 T["photons"].view(torch.int64)[idx].contiguous().view(T["photons"].dtype))
+        ref, _ = SP.mc_fractions(h, SP.with_photons(sub_prob, 1_000_000), 99 + len(ver))
+        torch.cuda.synchronize()
+        refn = ref.cpu().numpy()
+        ver[name] = {"designs": int(K),
+                     "surrogate_sweep_vs_1e6_mc": SP.errors(rat_s.view(n, 3)[idx].cpu().numpy().ravel(), refn),
+                     "plain_mc_vs_1e6_mc": SP.errors(rat_mc.view(n, 3)[idx].cpu().numpy().ravel(), refn),
+                     "fallback_frac": float(used[idx].float().mean().item())}
+        say(f"verified {name} {K} designs: {ver[name]}")
+    sps_sur = D / t_sur
+    sps_mc = D / t_mc
+    rec = {
+        "metric": "spectra/s: surrogate + Monte Carlo fallback vs plain GPU Monte Carlo (<=0.01 R/A/T error)",
+        "value": sps_sur, "unit": "spectra/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * t_sur, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MFMA / f32 walk", "data": "synthetic",
+        "config": {"workload": f"paint sweep: {D} single-layer designs x {L} wavelengths (0.3-16 um), "
+                               f"spread gate {args.spread_max}, fallback {args.fallback_photons} photons",
+                   "items": n},
+        "plain_mc_spectra_per_s": sps_mc, "plain_mc_seconds": t_mc, "plain_mc_photon_steps": steps_mc,
+        "speedup_vs_plain_mc_at_fallback_photons": sps_sur / sps_mc,
+        "speedup_vs_plain_mc_scaled": {"1e4": sps_sur / (sps_mc * args.fallback_photons / 1e4),
+                                       "1e5": sps_sur / (sps_mc * args.fallback_photons / 1e5),
+                                       "1e6": sps_sur / (sps_mc * args.fallback_photons / 1e6)},
+        "fallback_rate": n_fb / n, "training": rec_train, "held_out": rec_held, "verification": ver,
+        "wall_s": time.perf_counter() - t_start,
+    }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     print("[bench] start", file=sys.stderr, flush=True)
     ap = argparse.ArgumentParser()
@@ -211,12 +353,29 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
-    ap.add_argument("--workload", default="two_species_500", choices=["two_species_500", "stacks_3layer"],
-                    help="two_species_500 (default, the headline line) or stacks_3layer (batched sweep)")
+    ap.add_argument("--workload", default="two_species_500",
+                    choices=["two_species_500", "stacks_3layer", "surrogate"],
+                    help="two_species_500 (default, the headline line), stacks_3layer (batched sweep) or "
+                         "surrogate (training on walk labels + design sweep with Monte Carlo fallback)")
+    ap.add_argument("--train-samples", type=int, default=2_000_000)
+    ap.add_argument("--train-photons", type=int, default=100_000)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lambdas", type=int, default=200)
+    ap.add_argument("--spread-max", type=float, default=0.01)
+    ap.add_argument("--fallback-photons", type=int, default=100_000)
+    ap.add_argument("--verify-designs", type=int, default=20)
+    ap.add_argument("--save-data", default="", help="write the walk-labelled training and held-out sets (.npz)")
+    ap.add_argument("--load-data", default="", help="read training and held-out sets written by --save-data")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--save-model", default="")
+    ap.add_argument("--load-model", default="")
     ap.add_argument("--designs", type=int, default=4096, help="designs of the stacks_3layer sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args(argv)
+    if args.workload == "surrogate":
+        return surrogate_main(args)
     if args.workload == "stacks_3layer":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)

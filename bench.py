@@ -200,6 +200,11 @@ def sweep_main(args):
     return 0
 
 
+TRAIN_SEED = 20240931     # training items and their walks
+HELD_SEED = 777           # held-out items
+HELD_N = 10_000
+
+
 def surrogate_main(args):
     """Surrogate pipeline: walk-labelled training set (single layers, inputs
     log-uniform over the workloads' optical depths, `train_photons` each),
@@ -227,22 +232,26 @@ def surrogate_main(args):
         say(f"model loaded from {args.load_model}")
     else:
         if args.load_data:
+            # stored labels, re-joined to features regenerated from the same item seeds
             z = np.load(args.load_data)
-            x = torch.from_numpy(z["x"]).cuda()
+            n_tr, ph = int(z["n"]), int(z["photons"])
+            x, _, _, _ = SP.make_training_set(h, n_tr, ph, seed=TRAIN_SEED, label=False)
             y = torch.from_numpy(z["y"]).cuda()
-            rec_train = {"samples": int(len(z["y"]) // 3), "photons_each": int(z["photons"]),
+            rec_train = {"samples": n_tr, "photons_each": ph, "label_seconds": float(z["label_seconds"]),
+                         "label_photon_steps": int(z["label_steps"]),
                          "labels": f"loaded from {os.path.basename(args.load_data)}"}
-            say(f"training set loaded: {rec_train['samples']} samples")
+            say(f"training set loaded: {n_tr} samples")
         else:
-            x, y, steps, secs = SP.make_training_set(h, args.train_samples, args.train_photons, seed=20240931,
+            x, y, steps, secs = SP.make_training_set(h, args.train_samples, args.train_photons, seed=TRAIN_SEED,
                                                      log=say)
             rec_train = {"samples": args.train_samples, "photons_each": args.train_photons, "label_seconds": secs,
                          "label_photon_steps": steps, "label_photon_steps_per_s": steps / secs}
         if args.save_data:
-            xh0, yh0, _, _ = SP.make_training_set(h, 10_000, args.train_photons, seed=777, chunk=10_000)
-            np.savez(args.save_data, x=x.cpu().numpy(), y=y.cpu().numpy(), xh=xh0.cpu().numpy(),
-                     yh=yh0.cpu().numpy(), photons=args.train_photons)
-            say(f"training and held-out sets written to {args.save_data}")
+            _, yh0, _, _ = SP.make_training_set(h, HELD_N, args.train_photons, seed=HELD_SEED, chunk=HELD_N)
+            np.savez(args.save_data, y=y.cpu().numpy(), yh=yh0.cpu().numpy(), n=rec_train["samples"],
+                     photons=rec_train["photons_each"], label_seconds=rec_train["label_seconds"],
+                     label_steps=rec_train["label_photon_steps"])
+            say(f"training and held-out labels written to {args.save_data}")
         hist, tsec = SP.train(h, x, y, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_min=args.lr * 1e-2,
                               seed=5)
         rec_train.update({"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": tsec,
@@ -254,14 +263,15 @@ def surrogate_main(args):
     # held-out set drawn like the training set
     if args.load_data:
         z = np.load(args.load_data)
-        xh, yh = torch.from_numpy(z["xh"]).cuda(), torch.from_numpy(z["yh"]).cuda()
+        xh, _, _, _ = SP.make_training_set(h, HELD_N, int(z["photons"]), seed=HELD_SEED, chunk=HELD_N, label=False)
+        yh = torch.from_numpy(z["yh"]).cuda()
     else:
-        xh, yh, _, _ = SP.make_training_set(h, 10_000, args.train_photons, seed=777, chunk=10_000)
+        xh, yh, _, _ = SP.make_training_set(h, HELD_N, args.train_photons, seed=HELD_SEED, chunk=HELD_N)
     rh, sh, ih = SP.predict(h, xh)
     torch.cuda.synchronize()
     eh = SP.errors(rh.cpu().numpy(), yh.cpu().numpy())
     spread_h = sh.cpu().numpy()
-    rec_held = {"n": 10_000, "error_vs_mc": eh, "frac_spread_gt_max": float((spread_h > args.spread_max).mean()),
+    rec_held = {"n": HELD_N, "error_vs_mc": eh, "frac_spread_gt_max": float((spread_h > args.spread_max).mean()),
                 "frac_in_domain": float(ih.float().mean().item())}
     say(f"held-out error vs MC {eh}")
 
@@ -300,7 +310,7 @@ def surrogate_main(args):
     top = np.argsort(-fom)[:K]
     rnd = np.random.default_rng(3).choice(D, size=K, replace=False)
     ver = {}
-    for name, designs in (("top", top), ("random", rnd)):
+    for name, designs in ((("top", top), ("random", rnd)) if K > 0 else ()):
         items = (designs[:, None] * L + np.arange(L)[None, :]).ravel()
         sub = {k: v for k, v in W.item_geometry(wl).items()}
         T = prob.tensors
@@ -359,7 +369,7 @@ def main(argv=None):
                          "surrogate (training on walk labels + design sweep with Monte Carlo fallback)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-photons", type=int, default=100_000)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lambdas", type=int, default=200)
     ap.add_argument("--spread-max", type=float, default=0.01)
     ap.add_argument("--fallback-photons", type=int, default=100_000)
@@ -367,7 +377,7 @@ def main(argv=None):
     ap.add_argument("--save-data", default="", help="write the walk-labelled training and held-out sets (.npz)")
     ap.add_argument("--load-data", default="", help="read training and held-out sets written by --save-data")
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--save-model", default="")
     ap.add_argument("--load-model", default="")
     ap.add_argument("--designs", type=int, default=4096, help="designs of the stacks_3layer sweep")

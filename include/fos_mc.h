@@ -254,8 +254,8 @@ typedef struct {
 
 /* The 8 raw surrogate features of every item of a transport problem
  * (DEVICE arrays as in fos_mc_problem, layer 0 of each item):
- * log10(mu_s t + 1e-6), log10(mu_a t + 1e-6), g, n_layer, n_lower,
- * log10(k_lower + 1e-4), mu0, layer index (0).  x DEVICE float [n_items * 8];
+ * log10(mu_s t + 1e-6), log10(mu_a t + 1e-6), -log10(1 - g + 1e-3), n_layer,
+ * n_lower, log10(k_lower + 1e-4), mu0, layer index (0).  x DEVICE float [n_items * 8];
  * eligible DEVICE uint8 [n_items] (may be NULL) = 1 for single-layer items
  * lit from an upper medium of index 1 -- the only items the surrogate serves
  * (the paper's network likewise needs air or vacuum boundaries).

@@ -160,7 +160,10 @@ hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, h
 // features, standardisation, first layer
 // ---------------------------------------------------------------------------
 // Raw features of item i (single layer): log10(tau_s + 1e-6),
-// log10(tau_a + 1e-6), g, n_layer, n_lower, log10(k_lower + 1e-4), mu0, 0.
+// log10(tau_a + 1e-6), -log10(1 - g + 1e-3), n_layer, n_lower,
+// log10(k_lower + 1e-4), mu0, 0.  The anisotropy enters through log(1 - g):
+// near g = 1 the transport depends on the reduced depth tau_s (1 - g), which
+// the first layer then reaches as a sum of two features.
 // eligible = one layer and an upper medium of index 1.
 __global__ void features_kernel(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
                                 const float* g, const float* n_layer, const float* thickness,
@@ -174,7 +177,7 @@ __global__ void features_kernel(int n, int L, const int32_t* n_layers, const flo
     float* xi = x + (size_t)i * kFeatures;
     xi[0] = log10f(mu_s[o] * t + 1e-6f);
     xi[1] = log10f(mu_a[o] * t + 1e-6f);
-    xi[2] = g[o];
+    xi[2] = -log10f(1.001f - g[o]);
     xi[3] = n_layer[o];
     xi[4] = n_lower[i];
     xi[5] = log10f(k_lower[i] + 1e-4f);

@@ -68,9 +68,11 @@ def mc_fractions(ctx, prob, seed: int):
     return rat, steps
 
 
-def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000, log=None):
+def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000, log=None, label: bool = True):
     """n single-layer items labelled by the walk at `photons` each.
-    Returns (x [n*8], y [n*3], photon-steps, seconds)."""
+    Returns (x [n*8], y [n*3], photon-steps, seconds).  With label=False only
+    the features are made (y is None): the items are a function of
+    (n, seed, chunk), so stored labels can be re-joined to their features."""
     import torch
     xs, ys = [], []
     steps = 0
@@ -81,14 +83,15 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000
         prob = device_problem(arrays)
         x = torch.zeros(m * fos.SUR_FEATURES, dtype=torch.float32, device="cuda")
         fos.fos_sur_features(ctx, prob, x)
-        rat, s = mc_fractions(ctx, prob, seed + c)
         xs.append(x)
-        ys.append(rat)
-        steps += s
-        if log:
-            log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
+        if label:
+            rat, s = mc_fractions(ctx, prob, seed + c)
+            ys.append(rat)
+            steps += s
+            if log:
+                log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
     torch.cuda.synchronize()
-    return torch.cat(xs), torch.cat(ys), steps, time.perf_counter() - t0
+    return torch.cat(xs), (torch.cat(ys) if label else None), steps, time.perf_counter() - t0
 
 
 def train(ctx, x, y, epochs=30, batch=8192, lr=1e-3, lr_min=1e-5, seed=1):

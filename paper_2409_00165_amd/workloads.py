@@ -320,24 +320,29 @@ def optics_request(wl: Workload):
 # 3.2e3, tau_a 5e-4 .. 1.2e2, g 0 .. 0.995).
 TRAIN_TAU_S = (1e-7, 5e3)
 TRAIN_TAU_A = (1e-4, 3e2)
-TRAIN_G = (0.0, 0.999)
+TRAIN_G = (-0.1, 0.999)
 
 
 def surrogate_training_items(n: int, seed: int, photons: int = 100_000, thickness: float = 100.0):
     """Single-layer items for Monte Carlo labels: tau_s and tau_a log-uniform
-    over the box above, g uniform, matrix n ~ U[1.3, 1.7], substrate n ~
-    U[1, 3.5] (a quarter exactly 1, air), k ~ 0 for half else log-U[1e-3,
-    1e-1], incidence cosine ~ U[0.5, 1] (a quarter exactly 1), air above.
+    over the box above; g uniform over TRAIN_G for half the items, else with
+    1 - g log-uniform over the same range (the forward-peaked end, where the
+    transport follows tau_s (1 - g), gets its share); matrix n ~ U[1.3, 1.7];
+    substrate n ~ U[1, 3.5] (half exactly 1, air); k = 0 for half else
+    log-U[1e-3, 1e-1]; incidence cosine ~ U[0.5, 1] (half exactly 1); air
+    above.  The exact air / normal-incidence values are the ones the
+    single-layer designs use, so they are drawn often.
     Returns numpy arrays shaped like item_geometry() plus mu_s, mu_a, g."""
     rng = np.random.default_rng(seed)
     lu = lambda lo, hi: np.exp(rng.uniform(math.log(lo), math.log(hi), n))
     tau_s = lu(*TRAIN_TAU_S)
     tau_a = lu(*TRAIN_TAU_A)
-    g = rng.uniform(*TRAIN_G, n)
+    g = np.where(rng.uniform(size=n) < 0.5, rng.uniform(*TRAIN_G, n),
+                 1.0 - lu(1.0 - TRAIN_G[1], 1.0 - TRAIN_G[0]))
     n_m = rng.uniform(1.3, 1.7, n)
-    n_sub = np.where(rng.uniform(size=n) < 0.25, 1.0, rng.uniform(1.0, 3.5, n))
+    n_sub = np.where(rng.uniform(size=n) < 0.5, 1.0, rng.uniform(1.0, 3.5, n))
     k_sub = np.where(rng.uniform(size=n) < 0.5, 0.0, lu(1e-3, 1e-1))
-    mu0 = np.where(rng.uniform(size=n) < 0.25, 1.0, rng.uniform(0.5, 1.0, n))
+    mu0 = np.where(rng.uniform(size=n) < 0.5, 1.0, rng.uniform(0.5, 1.0, n))
     t = np.full(n, thickness)
     return {"n_layers": np.ones(n, np.int32), "mu_s": (tau_s / t)[:, None], "mu_a": (tau_a / t)[:, None],
             "g": g[:, None], "n_layer": n_m[:, None], "thickness": t[:, None], "n_upper": np.ones(n),

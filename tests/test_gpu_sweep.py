@@ -30,6 +30,35 @@ def _paint(n_designs=12, n_lambda=40):
     return W.paint_1layer(n_designs, n_lambda=n_lambda, photons=20_000)
 
 
+def test_features_match_host_formulas(torch):
+    """The 8 raw features and the eligibility flag against the same formulas
+    evaluated in FP64 on the problem's own (device) inputs."""
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    from paper_2409_00165_amd import workloads as W
+    c = fos.Context(0)
+    h = c.handle
+    for wl in (_paint(), W.stacks_3layer(n_designs=3, n_lambda=10, photons_lo=2e4, photons_hi=2e4)):
+        prob = SP.optics_problem(h, wl)
+        n, L = prob.n_items, prob.max_layers
+        x = torch.zeros(8 * n, device="cuda")
+        elig = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        fos.fos_sur_features(h, prob, x, elig)
+        torch.cuda.synchronize()
+        T = {k: v.cpu().numpy() for k, v in prob.tensors.items() if k != "photons"}
+        f64 = lambda k: T[k].astype(np.float64)
+        first = lambda k: f64(k).reshape(n, L)[:, 0]
+        t = first("thickness")
+        ref = np.stack([np.log10(first("mu_s") * t + 1e-6), np.log10(first("mu_a") * t + 1e-6),
+                        -np.log10(1.001 - first("g")), first("n_layer"), f64("n_lower"),
+                        np.log10(f64("k_lower") + 1e-4), f64("mu0"), np.zeros(n)], 1)
+        got = x.view(n, 8).cpu().numpy().astype(np.float64)
+        assert np.abs(got - ref).max() < 1e-4, np.abs(got - ref).max(0)
+        want = (T["n_layers"] == 1) & (T["n_upper"] == 1.0)
+        assert np.array_equal(elig.cpu().numpy().astype(bool), want)
+    c.close()
+
+
 def test_sweep_all_fallback_equals_plain_monte_carlo(trained, torch):
     from paper_2409_00165_amd import fos
     from paper_2409_00165_amd import surrogate_pipeline as SP

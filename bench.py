@@ -200,6 +200,9 @@ def sweep_main(args):
     return 0
 
 
+# forward FLOP of one row through one member: 2 x (8*256 + 3*256*256 + 256*3)
+MLP_FORWARD_FLOP = 2 * (8 * 256 + 3 * 256 * 256 + 256 * 3)
+BF16_MFMA_PEAK = 2.5e15   # dense BF16 MFMA, MI355X
 TRAIN_SEED = 20240931     # training items and their walks
 HELD_SEED = 777           # held-out items
 HELD_N = 10_000
@@ -234,6 +237,8 @@ def surrogate_main(args):
         if args.load_data:
             # stored labels, re-joined to features regenerated from the same item seeds
             z = np.load(args.load_data)
+            if str(z["recipe"]) != SP.training_recipe_id(TRAIN_SEED):
+                raise SystemExit(f"{args.load_data}: labels were drawn by another training-item recipe")
             n_tr, ph = int(z["n"]), int(z["photons"])
             x, _, _, _ = SP.make_training_set(h, n_tr, ph, seed=TRAIN_SEED, label=False)
             y = torch.from_numpy(z["y"]).cuda()
@@ -249,6 +254,7 @@ def surrogate_main(args):
         if args.save_data:
             _, yh0, _, _ = SP.make_training_set(h, HELD_N, args.train_photons, seed=HELD_SEED, chunk=HELD_N)
             np.savez(args.save_data, y=y.cpu().numpy(), yh=yh0.cpu().numpy(), n=rec_train["samples"],
+                     recipe=SP.training_recipe_id(TRAIN_SEED),
                      photons=rec_train["photons_each"], label_seconds=rec_train["label_seconds"],
                      label_steps=rec_train["label_photon_steps"])
             say(f"training and held-out labels written to {args.save_data}")
@@ -275,62 +281,79 @@ def surrogate_main(args):
                 "frac_in_domain": float(ih.float().mean().item())}
     say(f"held-out error vs MC {eh}")
 
-    # the sweep
-    wl = W.paint_1layer(args.designs, n_lambda=args.lambdas, photons=args.fallback_photons)
-    prob = SP.optics_problem(h, wl)
+    # the sweep: optics of every design on the GPU (log-normal size grid)
+    sweep = W.paint_sweep(args.designs, n_lambda=args.lambdas, photons=args.fallback_photons)
+    t0 = time.perf_counter()
+    prob = SP.paint_problem(h, sweep)
+    torch.cuda.synchronize()
+    t_optics = time.perf_counter() - t0
     n = prob.n_items
     D, L = args.designs, args.lambdas
-    torch.cuda.synchronize()
-    say(f"sweep problem ready: {D} designs x {L} wavelengths")
+    say(f"sweep problem ready: {D} designs x {L} wavelengths ({t_optics:.2f} s of optics)")
+    # plain Monte Carlo at the fallback budget, on the first `mc_designs` designs
+    Dm = min(args.mc_designs, D)
+    sub = SP.take_items(prob, torch.arange(Dm * L, device="cuda"))
     t0 = time.perf_counter()
-    rat_mc, steps_mc = SP.mc_fractions(h, prob, 424242)
+    _, steps_mc = SP.mc_fractions(h, sub, 424242)
     torch.cuda.synchronize()
     t_mc = time.perf_counter() - t0
-    say(f"plain Monte Carlo sweep {t_mc:.2f} s")
+    del sub
+    say(f"plain Monte Carlo on {Dm} designs {t_mc:.2f} s")
     rat_s = torch.zeros(3 * n, device="cuda")
     used = torch.zeros(n, dtype=torch.uint8, device="cuda")
     spread = torch.zeros(n, device="cuda")
+    say("surrogate + fallback sweep: warm-up call")
     fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515151, rat_s, used, spread=spread)
     torch.cuda.synchronize()
+    say("surrogate + fallback sweep: timed call")
     t0 = time.perf_counter()
     n_fb = fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515152, rat_s, used, spread=spread)
     torch.cuda.synchronize()
     t_sur = time.perf_counter() - t0
-    say(f"surrogate + fallback sweep {t_sur:.3f} s, {n_fb} of {n} items on Monte Carlo")
+    n_spread = int((spread > args.spread_max).sum().item())
+    say(f"surrogate + fallback sweep {t_sur:.3f} s, {n_fb} of {n} items on Monte Carlo "
+        f"({n_spread} by spread, {n_fb - n_spread} outside the training box)")
+    # the fused inference kernel alone over every item (features already made),
+    # timed with events on the stream it runs on: the MFMA roofline
+    xs_all = torch.zeros(8 * n, device="cuda")
+    el_all = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fos.fos_sur_features(h, prob, xs_all, el_all)
+    pr_rat = torch.zeros(3 * n, device="cuda")
+    fos.fos_sur_predict(h, xs_all, eligible=el_all, rat=pr_rat)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    fos.fos_sur_predict(h, xs_all, eligible=el_all, rat=pr_rat)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_pred = ev0.elapsed_time(ev1) / 1e3
+    del xs_all, el_all, pr_rat
+    pred_flop = float(MLP_FORWARD_FLOP) * 4 * n
+    say(f"fused ensemble inference over {n} rows: {t_pred * 1e3:.1f} ms, {pred_flop / t_pred / 1e12:.1f} TFLOP/s")
     # reductions: solar-weighted R (5778 K Planck stand-in) and 8-13 um emittance
-    lam = wl.wavelengths
+    lam = sweep.wavelengths
     wr = torch.from_numpy(W.planck_weights(lam, 5778.0, 0.3, 2.5).astype(np.float32)).cuda()
     we = torch.from_numpy(W.planck_weights(lam, 300.0, 8.0, 13.0).astype(np.float32)).cuda()
     red_s = torch.zeros(2 * D, device="cuda")
-    red_m = torch.zeros(2 * D, device="cuda")
     fos.fos_spectral_reduce(h, D, L, rat_s, wr, we, red_s)
-    fos.fos_spectral_reduce(h, D, L, rat_mc, wr, we, red_m)
     fom = red_s.view(D, 2).sum(1).cpu().numpy()
     K = min(args.verify_designs, D)
     top = np.argsort(-fom)[:K]
     rnd = np.random.default_rng(3).choice(D, size=K, replace=False)
     ver = {}
     for name, designs in ((("top", top), ("random", rnd)) if K > 0 else ()):
-        items = (designs[:, None] * L + np.arange(L)[None, :]).ravel()
-        sub = {k: v for k, v in W.item_geometry(wl).items()}
-        T = prob.tensors
-        idx = torch.from_numpy(items).cuda()
-        sub_prob = fos.MCProblem(T["n_layers"][idx].contiguous(), T["mu_s"][idx].contiguous(),
-                                 T["mu_a"][idx].contiguous(), T["g"][idx].contiguous(),
-                                 T["n_layer"][idx].contiguous(), T["thickness"][idx].contiguous(),
-                                 T["n_upper"][idx].contiguous(), T["n_lower"][idx].contiguous(),
-                                 T["k_lower"][idx].contiguous(), T["mu0"][idx].contiguous(),
-                                 T["photons"].view(torch.int64)[idx].contiguous().view(T["photons"].dtype))
-        ref, _ = SP.mc_fractions(h, SP.with_photons(sub_prob, 1_000_000), 99 + len(ver))
+        items = torch.from_numpy((designs[:, None] * L + np.arange(L)[None, :]).ravel()).cuda()
+        vprob = SP.take_items(prob, items)
+        ref, _ = SP.mc_fractions(h, SP.with_photons(vprob, 1_000_000), 99 + len(ver))
+        plain, _ = SP.mc_fractions(h, SP.with_photons(vprob, args.fallback_photons), 77 + len(ver))
         torch.cuda.synchronize()
         refn = ref.cpu().numpy()
         ver[name] = {"designs": int(K),
-                     "surrogate_sweep_vs_1e6_mc": SP.errors(rat_s.view(n, 3)[idx].cpu().numpy().ravel(), refn),
-                     "plain_mc_vs_1e6_mc": SP.errors(rat_mc.view(n, 3)[idx].cpu().numpy().ravel(), refn),
-                     "fallback_frac": float(used[idx].float().mean().item())}
+                     "surrogate_sweep_vs_1e6_mc": SP.errors(rat_s.view(n, 3)[items].cpu().numpy().ravel(), refn),
+                     "plain_mc_vs_1e6_mc": SP.errors(plain.cpu().numpy(), refn),
+                     "fallback_frac": float(used[items].float().mean().item())}
         say(f"verified {name} {K} designs: {ver[name]}")
     sps_sur = D / t_sur
-    sps_mc = D / t_mc
+    sps_mc = Dm / t_mc
     rec = {
         "metric": "spectra/s: surrogate + Monte Carlo fallback vs plain GPU Monte Carlo (<=0.01 R/A/T error)",
         "value": sps_sur, "unit": "spectra/s", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -339,12 +362,19 @@ def surrogate_main(args):
         "config": {"workload": f"paint sweep: {D} single-layer designs x {L} wavelengths (0.3-16 um), "
                                f"spread gate {args.spread_max}, fallback {args.fallback_photons} photons",
                    "items": n},
-        "plain_mc_spectra_per_s": sps_mc, "plain_mc_seconds": t_mc, "plain_mc_photon_steps": steps_mc,
+        "optics_seconds": t_optics,
+        "plain_mc_spectra_per_s": sps_mc, "plain_mc_seconds": t_mc, "plain_mc_designs": Dm,
+        "plain_mc_photon_steps": steps_mc,
         "speedup_vs_plain_mc_at_fallback_photons": sps_sur / sps_mc,
         "speedup_vs_plain_mc_scaled": {"1e4": sps_sur / (sps_mc * args.fallback_photons / 1e4),
                                        "1e5": sps_sur / (sps_mc * args.fallback_photons / 1e5),
                                        "1e6": sps_sur / (sps_mc * args.fallback_photons / 1e6)},
-        "fallback_rate": n_fb / n, "training": rec_train, "held_out": rec_held, "verification": ver,
+        "roofline": {"bound": "mfma", "achieved": pred_flop / t_pred / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": pred_flop / t_pred / BF16_MFMA_PEAK, "traffic": None,
+                     "kernel": "fos::mlp_infer_kernel", "rows": n, "kernel_ms": 1e3 * t_pred,
+                     "work_per_row_flop": 4 * MLP_FORWARD_FLOP},
+        "fallback_rate": n_fb / n, "fallback_by_spread": n_spread, "fallback_out_of_domain": n_fb - n_spread,
+        "training": rec_train, "held_out": rec_held, "verification": ver,
         "wall_s": time.perf_counter() - t_start,
     }
     ctx.close()
@@ -374,6 +404,8 @@ def main(argv=None):
     ap.add_argument("--spread-max", type=float, default=0.01)
     ap.add_argument("--fallback-photons", type=int, default=100_000)
     ap.add_argument("--verify-designs", type=int, default=20)
+    ap.add_argument("--mc-designs", type=int, default=4096,
+                    help="designs of the sweep timed with plain Monte Carlo (the first ones)")
     ap.add_argument("--save-data", default="", help="write the walk-labelled training and held-out sets (.npz)")
     ap.add_argument("--load-data", default="", help="read training and held-out sets written by --save-data")
     ap.add_argument("--lr", type=float, default=1e-3)

@@ -228,6 +228,47 @@ typedef struct {
 fos_status fos_optics_run(fos_ctx* ctx, const fos_optics_problem* problem, float* mu_s, float* mu_a,
                           float* g, double* out_f64, void* hip_stream);
 
+/* Log-normal particle populations on a shared size grid: the same optics
+ * as fos_optics_run for designs whose particles are one species in log-normal
+ * sizes binned as the workloads bin them (n_bins equal bins of width dlnr in
+ * ln r, centred on ln r_med, volume weights w[b]), with the median radius on
+ * the grid r_med = r0 exp(k dlnr).  Every bin of every design then lies on the
+ * radius grid r_j = r0 exp((j - (n_bins - 1)/2) dlnr), j = 0 .. n_rmed +
+ * n_bins - 2, so the Lorenz-Mie efficiencies are evaluated once per (species,
+ * matrix, wavelength, r_j) and eqs. (13)-(16) become per-(median, wavelength)
+ * bin sums times the design's volume fraction f (f_i = f w[b]); the clamp,
+ * eqs. (17)-(19) and (20) follow per design exactly as in fos_optics_run.
+ * HOST arrays: lambda, n_p, k_p, n_m, w.  DEVICE arrays: species, matrix,
+ * rmed, f.  Outputs DEVICE float [n_designs * n_lambda], design-major: the
+ * per-layer arrays of single-layer items (item = design * n_lambda + l).
+ * Valid: lambda > 0, n_p > 0, k_p >= 0, n_m > 0, k_m >= 0, r0 > 0,
+ * dlnr > 0, n_bins >= 1, w >= 0, indices in range, 0 <= f <= 1.
+ * Synchronises `hip_stream` (validation verdict); FOS_E_INVALID_ARG names the
+ * first bad design or table field. */
+typedef struct {
+    int32_t n_lambda;
+    const double* lambda;    /* HOST [n_lambda] micrometres */
+    int32_t n_species;
+    const double* n_p;       /* HOST [n_species * n_lambda] particle index, real part */
+    const double* k_p;       /* HOST [n_species * n_lambda] particle index, imaginary part */
+    int32_t n_matrix;
+    const double* n_m;       /* HOST [n_matrix] matrix index, real part */
+    double k_m;              /* matrix index, imaginary part (all matrices) */
+    double r0;               /* smallest median radius, micrometres */
+    double dlnr;             /* bin width and median-grid spacing in ln r */
+    int32_t n_rmed;          /* median radii on the grid */
+    int32_t n_bins;
+    const double* w;         /* HOST [n_bins] volume weights of the bins */
+    int32_t n_designs;
+    const int32_t* species;  /* DEVICE [n_designs] */
+    const int32_t* matrix;   /* DEVICE [n_designs] index into n_m */
+    const int32_t* rmed;     /* DEVICE [n_designs] median-radius index */
+    const double* f;         /* DEVICE [n_designs] total particle volume fraction */
+} fos_lognormal_problem;
+
+fos_status fos_optics_lognormal(fos_ctx* ctx, const fos_lognormal_problem* problem, float* mu_s, float* mu_a,
+                                float* g, void* hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Surrogate network (the paper's neural-network alternative to Monte Carlo,  */
 /* Methodology, Photon transport; trained here on this library's own walk)    */

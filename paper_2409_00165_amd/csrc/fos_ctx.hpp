@@ -21,6 +21,7 @@ struct fos_sur_state {
     float* v = nullptr;          // Adam second moment
     float* grads = nullptr;      // [4][kParams]
     __bf16* wb = nullptr;        // [4][kBfParams] bf16 copies
+    __bf16* pk = nullptr;        // [4][kPkParams] fragment-ordered copies for fused inference
     float* stats = nullptr;      // [32] mean, 1/std, min, max (device)
     float stats_host[32] = {};
     // workspaces, sized for `rows` rows per member
@@ -37,7 +38,9 @@ struct fos_sur_state {
     // sweep scratch
     std::vector<void*> sweep;    // freed together
     int64_t sweep_cap = 0;
-    int sweep_layers = 0;
+    std::vector<void*> sub;      // fallback sub-problem, freed together
+    int64_t sub_cap = 0;
+    int sub_layers = 0;
     float* sx = nullptr; uint8_t* selig = nullptr; uint8_t* sdom = nullptr; float* sspread = nullptr;
     unsigned long long* sblock = nullptr; int64_t* sidx = nullptr; unsigned long long* stotal = nullptr;
     int32_t* sub_nl = nullptr; float* sub_l[5] = {}; float* sub_i[4] = {}; uint64_t* sub_ph = nullptr;
@@ -68,6 +71,8 @@ struct fos_ctx {
     size_t mie_bytes = 0;
     double2* mie_scratch = nullptr;
     size_t mie_scratch_bytes = 0;
+    double* ln_buf = nullptr;                 // log-normal grid cells, radii, weights, bin-sum table
+    size_t ln_buf_bytes = 0;
     unsigned int* nmax_dev = nullptr;        // device, 1 word
     unsigned long long* aux_host = nullptr;  // pinned host, 4 words
     // tuning and graph

@@ -72,6 +72,28 @@ struct OpticsArgs {
     double* out_f64;              // [n_cells * 3] or NULL
 };
 
+// log-normal populations on a shared radius grid (fos_optics_lognormal)
+enum LnErrCode : int { kLnErrSpecies = 1, kLnErrMatrix = 2, kLnErrRmed = 3, kLnErrFraction = 4 };
+
+struct LognormalArgs {
+    int n_lambda, n_species, n_matrix, n_rmed, n_bins, n_radii;
+    const double* mie;      // [(species * n_matrix + matrix) * n_lambda + l][n_radii][3] efficiencies
+    const double* radii;    // [n_radii]
+    const double* w;        // [n_bins]
+    const double* lam;      // [n_lambda]
+    double k_m;
+    double* table;          // [(species * n_matrix + matrix) * n_lambda + l][n_rmed][3] bin sums
+    int n_designs;
+    const int32_t *species, *matrix, *rmed;
+    const double* f;
+    unsigned long long* err;
+    float *out_mu_s, *out_mu_a, *out_g;
+};
+
+hipError_t launch_lognormal_check(const LognormalArgs& a, hipStream_t st);
+hipError_t launch_lognormal_table(const LognormalArgs& a, hipStream_t st);
+hipError_t launch_lognormal_cells(const LognormalArgs& a, hipStream_t st);
+
 hipError_t launch_optics_scan(const OpticsArgs& a, hipStream_t st);
 hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st);
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);

@@ -39,6 +39,28 @@ constexpr size_t kBfW5p = kBfW4 + (size_t)kHidden * kHidden;
 constexpr size_t kBfW5t = kBfW5p + (size_t)kHidden * kPadOut;
 constexpr size_t kBfParams = kBfW5t + (size_t)kHidden * kPadK5;
 
+// fragment-ordered bf16 weights of one member for the fused inference kernel
+// (mlp_infer.hip): layer 1 (hi/lo split), hidden layers 2..4, output layer
+constexpr size_t kPkHid = (size_t)16 * 8 * 64 * 8;    // 16 neuron tiles x 8 k-steps x 64 lanes x 8
+constexpr size_t kPkOffL1 = 0;
+constexpr size_t kPkOffL2 = kPkOffL1 + (size_t)16 * 64 * 8;
+constexpr size_t kPkOffOut = kPkOffL2 + 3 * kPkHid;
+constexpr size_t kPkParams = kPkOffOut + (size_t)8 * 64 * 8;
+constexpr int kInferTile = 128;                        // rows per inference workgroup
+
+struct InferArgs {
+    int64_t n;
+    const float* x;              // raw features [n][8]
+    const uint8_t* eligible;     // [n] or null (all eligible)
+    const float* stats;          // mean[8], 1/std[8], box min[8], box max[8]
+    const float* params;         // fp32 masters [nets][kParams] (biases)
+    const __bf16* pk;            // [nets][kPkParams]
+    float* rat;                  // [n][3] ensemble mean, or null
+    float* spread;               // [n] or null
+    uint8_t* in_domain;          // [n] or null
+    float* members;              // [nets][n][3] or null
+};
+
 enum Epilogue : int { kEpiStore = 0, kEpiBiasGelu = 1, kEpiGeluGrad = 2 };
 
 struct GemmArgs {
@@ -84,16 +106,6 @@ struct AdamArgs {
     float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t)
 };
 
-struct GateArgs {
-    int rows, rows_pad, nets;
-    int64_t out_offset, n_total;
-    const float* probs;          // [nets][rows_pad][3]
-    const float* x;              // raw features of these rows [rows][8]
-    const uint8_t* eligible;     // or null
-    const float* lo; const float* hi;
-    float* rat; float* spread; uint8_t* in_domain; float* members;
-};
-
 // sweep: fallback selection, compaction, gather/scatter of sub-problems
 struct SweepSelectArgs {
     int64_t n;
@@ -125,6 +137,8 @@ hipError_t launch_scatter_mc(int64_t m, const int64_t* idx, const unsigned long 
 hipError_t launch_spectral_reduce(int designs, int lambdas, const float* rat, const float* w_r, const float* w_e,
                                   float* out, hipStream_t st);
 
+hipError_t launch_pack_infer(const float* params, __bf16* pk, int nets, hipStream_t st);
+hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st);
 hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
                            const float* g, const float* n_layer, const float* thickness, const float* n_upper,
@@ -140,7 +154,6 @@ hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int r
                              size_t dstride, int nets, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st);
 hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t st);
-hipError_t launch_ensemble_gate(const GateArgs& a, hipStream_t st);
 hipError_t launch_feature_stats(const float* x, int64_t n, float* stats, hipStream_t st);
 hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st);
 

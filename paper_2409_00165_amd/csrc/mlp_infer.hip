@@ -1,0 +1,305 @@
+// mlp_infer.hip -- fused ensemble inference of the surrogate network with its
+// validity gate: one workgroup carries a tile of rows through all five layers
+// of all four members without leaving the CU, then writes the ensemble mean,
+// the spread and the domain flag.
+//
+// Per member the rows see: standardise -> 8 -> 256 (GELU) -> 256 (GELU) ->
+// 256 (GELU) -> 256 (GELU) -> 3 -> softmax, the same network the training
+// kernels (mlp_kernels.hip) fit.  Every product runs on
+// v_mfma_f32_16x16x32_bf16 with fp32 accumulation:
+//   * the 8-wide input layer keeps fp32-like accuracy by splitting inputs and
+//     weights into bf16 high and low parts: one K=32 product holds
+//     W_hi x_hi + W_hi x_lo + W_lo x_hi (the dropped W_lo x_lo term is below
+//     2^-16 relative);
+//   * hidden layers multiply bf16 weights by the bf16 activations kept in LDS;
+//   * the output layer pads its 3 neurons to one 16-wide tile.
+// The products are computed transposed (neurons x rows): the weights are the
+// A operand, streamed from L2 in a pre-swizzled fragment order (one coalesced
+// 1 KB load per 16 x 32 fragment), and the activations are the B operand read
+// from LDS.  A lane's accumulator then holds 4 consecutive neurons of one
+// row, so the bias + GELU epilogue writes 8-byte bf16 quads back to LDS.
+//
+// Work split inside a workgroup (4 waves, 128 rows): wave w owns neurons
+// 64w .. 64w+63 of every hidden layer for all 128 rows (32 accumulator tiles)
+// and rows 32w .. 32w+31 of the output layer; the lanes that end with a row's
+// logits keep that row's ensemble sum / min / max in registers across the
+// members.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fos_mlp.hpp"
+
+namespace fos {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = kInferTile;            // rows per workgroup
+constexpr int kHRow = kHidden + 8;           // bf16 per LDS activation row (528 B: conflict-free b128 reads)
+constexpr int kXRow = 32 + 8;                // bf16 per LDS input-fragment row
+
+// gelu(z) = 0.5 z (1 + tanh(u)), u = sqrt(2/pi)(z + 0.044715 z^3), evaluated
+// as z * sigmoid(2u) = z / (1 + 2^(z (k1 + k2 z^2))); saturates to 0 and z
+// at the two ends without NaN.
+constexpr float kG1 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kG2 = kG1 * 0.044715f;
+
+__device__ __forceinline__ float gelu_sig(float z)
+{
+    const float t = z * fmaf(kG2, z * z, kG1);
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
+}
+
+__device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const floatx4& c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// bias + GELU of a wave's 64 neurons x 128 rows, written to H as bf16 quads
+__device__ __forceinline__ void epilogue(floatx4 (&acc)[4][kTile / 16], const float* __restrict__ bias, __bf16* H,
+                                         int w, int q, int c16)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n0 = 16 * (4 * w + j) + 4 * q;
+        const float b0 = bias[n0], b1 = bias[n0 + 1], b2 = bias[n0 + 2], b3 = bias[n0 + 3];
+#pragma unroll
+        for (int i = 0; i < kTile / 16; ++i) {
+            bf16x4 v;
+            v[0] = (__bf16)gelu_sig(acc[j][i][0] + b0);
+            v[1] = (__bf16)gelu_sig(acc[j][i][1] + b1);
+            v[2] = (__bf16)gelu_sig(acc[j][i][2] + b2);
+            v[3] = (__bf16)gelu_sig(acc[j][i][3] + b3);
+            *reinterpret_cast<bf16x4*>(H + (16 * i + c16) * kHRow + n0) = v;
+        }
+    }
+}
+
+}  // namespace
+
+// Fragment-ordered bf16 weights of every member from the fp32 masters.
+//   layer 1 : [16 neuron tiles][64 lanes][8]; lane l of tile t holds neuron
+//             16t + l%16 and, by quarter q = l/16: q0 W_hi[0..7], q1 W_hi[0..7],
+//             q2 W_lo[0..7], q3 zero (matching x_hi, x_lo, x_hi, 0 in B).
+//   hidden  : [16 neuron tiles][8 k-steps][64 lanes][8]: neuron 16t + l%16,
+//             inputs 32s + 8q .. 32s + 8q + 7.
+//   output  : [8 k-steps][64 lanes][8]: neuron l%16 (zero beyond 3).
+__global__ void pack_infer_kernel(const float* __restrict__ params, __bf16* __restrict__ pk)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (e >= kPkParams) return;
+    const float* P = params + (size_t)m * kParams;
+    float v = 0.0f;
+    if (e < kPkOffL2) {
+        const int t = (int)(e / 512), l = (int)(e / 8) % 64, j = (int)(e % 8), q = l / 16;
+        const int n = 16 * t + l % 16;
+        const float w = P[kOffW1 + j * kHidden + n];
+        const float hi = (float)(__bf16)w;
+        v = q == 3 ? 0.0f : (q == 2 ? w - hi : w);
+    } else if (e < kPkOffOut) {
+        const size_t r = (e - kPkOffL2) % kPkHid;
+        const int layer = (int)((e - kPkOffL2) / kPkHid);
+        const int t = (int)(r / 4096), s = (int)(r / 512) % 8, l = (int)(r / 8) % 64, j = (int)(r % 8);
+        const int n = 16 * t + l % 16, k = 32 * s + 8 * (l / 16) + j;
+        const size_t off = layer == 0 ? kOffW2 : layer == 1 ? kOffW3 : kOffW4;
+        v = P[off + (size_t)k * kHidden + n];
+    } else {
+        const size_t r = e - kPkOffOut;
+        const int s = (int)(r / 512), l = (int)(r / 8) % 64, j = (int)(r % 8);
+        const int n = l % 16, k = 32 * s + 8 * (l / 16) + j;
+        v = n < 3 ? P[kOffW5 + k * 3 + n] : 0.0f;
+    }
+    pk[(size_t)m * kPkParams + e] = (__bf16)v;
+}
+
+__global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 H[kTile * kHRow];
+    __shared__ __attribute__((aligned(16))) __bf16 X[kTile * kXRow];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
+    const int64_t row0 = (int64_t)blockIdx.x * kTile;
+
+    // standardised inputs split into bf16 high / low parts: X[r] = x_hi, x_lo, x_hi, 0
+    if (tid < kTile) {
+        const int64_t row = row0 + tid;
+        bf16x8 hi8, lo8;
+#pragma unroll
+        for (int k = 0; k < kFeatures; ++k) {
+            float v = 0.0f;
+            if (row < a.n) v = (a.x[row * kFeatures + k] - a.stats[k]) * a.stats[kFeatures + k];
+            const __bf16 h = (__bf16)v;
+            hi8[k] = h;
+            lo8[k] = (__bf16)(v - (float)h);
+        }
+        __bf16* xr = X + tid * kXRow;
+        *reinterpret_cast<bf16x8*>(xr) = hi8;
+        *reinterpret_cast<bf16x8*>(xr + 8) = lo8;
+        *reinterpret_cast<bf16x8*>(xr + 16) = hi8;
+        bf16x8 z8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) z8[k] = (__bf16)0.0f;
+        *reinterpret_cast<bf16x8*>(xr + 24) = z8;
+    }
+
+    float sum[2][3], mn[2][3], mx[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { sum[i][c] = 0.0f; mn[i][c] = 1e30f; mx[i][c] = -1e30f; }
+
+    const floatx4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < kNets; ++m) {
+        const __bf16* P = a.pk + (size_t)m * kPkParams;
+        const float* F = a.params + (size_t)m * kParams;
+        floatx4 acc[4][kTile / 16];
+
+        // layer 1: one K=32 product per tile
+        __syncthreads();   // X written / previous member's output layer done with H
+        {
+            bf16x8 wf[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                wf[j] = *reinterpret_cast<const bf16x8*>(P + kPkOffL1 + ((size_t)(4 * w + j) * 64 + lane) * 8);
+#pragma unroll
+            for (int i = 0; i < kTile / 16; ++i) {
+                const bf16x8 xf = *reinterpret_cast<const bf16x8*>(X + (16 * i + c16) * kXRow + 8 * q);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wf[j], xf, zero4);
+            }
+        }
+        epilogue(acc, F + kOffB1, H, w, q, c16);
+
+        // hidden layers 2..4, in place in H.  The weight fragments of k-step
+        // s + 1 are in flight while k-step s multiplies (two register sets
+        // used in turn, so every wait is for loads issued a step earlier).
+#pragma unroll 1
+        for (int layer = 0; layer < 3; ++layer) {
+            const __bf16* W = P + kPkOffL2 + (size_t)layer * kPkHid + ((size_t)(4 * w) * 8 * 64 + lane) * 8;
+            const size_t boff = layer == 0 ? kOffB2 : layer == 1 ? kOffB3 : kOffB4;
+            auto load = [&](bf16x8 (&f)[4], int s) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    f[j] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(j * 8 + s) * 64) * 8);
+            };
+            auto step = [&](const bf16x8 (&f)[4], int s) {
+#pragma unroll
+                for (int i = 0; i < kTile / 16; ++i) {
+                    const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + (16 * i + c16) * kHRow + 32 * s + 8 * q);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[j][i] = mfma(f[j], hf, acc[j][i]);
+                }
+            };
+            bf16x8 wa[4], wb[4];
+            load(wa, 0);
+            load(wb, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();   // H of the previous layer complete
+#pragma unroll
+            for (int i = 0; i < kTile / 16; ++i) {
+                const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + (16 * i + c16) * kHRow + 8 * q);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wa[j], hf, zero4);
+            }
+            // the scheduling barriers keep each prefetch ahead of the products
+            // it overlaps (left alone, the scheduler sinks the loads past them)
+#pragma unroll 1
+            for (int t = 0; t < 3; ++t) {
+                load(wa, 2 * t + 2);
+                __builtin_amdgcn_sched_barrier(0);
+                step(wb, 2 * t + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                load(wb, 2 * t + 3);
+                __builtin_amdgcn_sched_barrier(0);
+                step(wa, 2 * t + 2);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            step(wb, 7);
+            __syncthreads();   // every wave done reading this layer's input
+            epilogue(acc, F + boff, H, w, q, c16);
+        }
+
+        // output layer: wave w takes rows 32w .. 32w+31 (two tiles)
+        __syncthreads();
+        floatx4 o[2] = {zero4, zero4};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const bf16x8 wf = *reinterpret_cast<const bf16x8*>(P + kPkOffOut + ((size_t)s * 64 + lane) * 8);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 hf =
+                    *reinterpret_cast<const bf16x8*>(H + (16 * (2 * w + i) + c16) * kHRow + 32 * s + 8 * q);
+                o[i] = mfma(wf, hf, o[i]);
+            }
+        }
+        if (q == 0) {   // lanes 0..15 hold logits 0..3 of rows 32w + 16i + lane
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                float l[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) l[c] = o[i][c] + F[kOffB5 + c];
+                const float lm = fmaxf(l[0], fmaxf(l[1], l[2]));
+                float e[3], se = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { e[c] = __expf(l[c] - lm); se += e[c]; }
+                const float is = 1.0f / se;
+                const int64_t row = row0 + 32 * w + 16 * i + c16;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // the rounded probability is what the members output holds;
+                    // no contraction, so the mean is the same sum of the same
+                    // values whichever register tile the row sits in
+#pragma clang fp contract(off)
+                    const float p = e[c] * is;
+                    sum[i][c] = sum[i][c] + p;
+                    mn[i][c] = fminf(mn[i][c], p);
+                    mx[i][c] = fmaxf(mx[i][c], p);
+                    if (a.members && row < a.n) a.members[((size_t)m * a.n + row) * 3 + c] = p;
+                }
+            }
+        }
+    }
+
+    if (q == 0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t row = row0 + 32 * w + 16 * i + c16;
+            if (row >= a.n) continue;
+            float spread = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) spread = fmaxf(spread, mx[i][c] - mn[i][c]);
+            const float* xr = a.x + row * kFeatures;
+            bool in = a.eligible ? a.eligible[row] != 0 : true;
+#pragma unroll
+            for (int k = 0; k < kFeatures; ++k)
+                in = in && xr[k] >= a.stats[2 * kFeatures + k] && xr[k] <= a.stats[3 * kFeatures + k];
+            if (a.rat)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a.rat[row * 3 + c] = sum[i][c] / (float)kNets;
+            if (a.spread) a.spread[row] = spread;
+            if (a.in_domain) a.in_domain[row] = in ? 1 : 0;
+        }
+    }
+}
+
+hipError_t launch_pack_infer(const float* params, __bf16* pk, int nets, hipStream_t st)
+{
+    hipLaunchKernelGGL(pack_infer_kernel, dim3((unsigned)((kPkParams + 255) / 256), nets), dim3(256), 0, st, params,
+                       pk);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int64_t blocks = (a.n + kTile - 1) / kTile;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace fos

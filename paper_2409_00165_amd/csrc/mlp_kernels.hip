@@ -20,8 +20,7 @@
 //                     Carlo fractions, d loss / d logits = (p - y) / B.
 //   colsum          : bias gradients (two-stage, deterministic).
 //   adam            : Adam on fp32 master weights, refreshing bf16 copies.
-//   ensemble_gate   : member mean, spread (max over channels of max - min),
-//                     training-box domain test.
+// Prediction (network + ensemble gate) is one fused kernel in mlp_infer.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -358,34 +357,6 @@ __global__ void accumulate_kernel(const float* src, float* dst, int n, float sca
 
 // member mean, spread = max_c (max_m p - min_m p), domain test of the raw
 // features against the training box, and the fallback decision
-__global__ void ensemble_gate_kernel(GateArgs a)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.rows) return;
-    float mean[3] = {0.f, 0.f, 0.f}, spread = 0.f;
-    for (int c = 0; c < 3; ++c) {
-        float lo = 1e30f, hi = -1e30f, s = 0.f;
-        for (int m = 0; m < a.nets; ++m) {
-            const float p = a.probs[((size_t)m * a.rows_pad + r) * 3 + c];
-            lo = fminf(lo, p); hi = fmaxf(hi, p); s += p;
-        }
-        mean[c] = s / (float)a.nets;
-        spread = fmaxf(spread, hi - lo);
-    }
-    const float* x = a.x + (size_t)r * kFeatures;
-    bool in = a.eligible ? a.eligible[r] != 0 : true;
-    for (int k = 0; k < kFeatures; ++k) in = in && x[k] >= a.lo[k] && x[k] <= a.hi[k];
-    const size_t o = (size_t)a.out_offset + r;
-    if (a.rat)
-        for (int c = 0; c < 3; ++c) a.rat[o * 3 + c] = mean[c];
-    if (a.spread) a.spread[o] = spread;
-    if (a.in_domain) a.in_domain[o] = in ? 1 : 0;
-    if (a.members)
-        for (int m = 0; m < a.nets; ++m)
-            for (int c = 0; c < 3; ++c)
-                a.members[((size_t)m * a.n_total + o) * 3 + c] = a.probs[((size_t)m * a.rows_pad + r) * 3 + c];
-}
-
 // per-feature mean, 1/std and min/max of n raw rows (one block, 8 x 128 threads)
 __global__ void feature_stats_kernel(const float* x, int64_t n, float* stats)
 {
@@ -657,13 +628,6 @@ hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t
 hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st)
 {
     hipLaunchKernelGGL(accumulate_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_ensemble_gate(const GateArgs& a, hipStream_t st)
-{
-    if (a.rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ensemble_gate_kernel, dim3((a.rows + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

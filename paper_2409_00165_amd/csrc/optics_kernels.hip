@@ -13,6 +13,12 @@
 //                 three series of eqs. (11), (12), (15).
 //   emt_cells   : per cell -- eqs. (13)-(16), the clamp, the dependent-
 //                 scattering factor (17)-(19) and matrix absorption (20).
+//   lognormal_* : log-normal populations whose bins lie on one radius grid:
+//                 per (species, matrix, wavelength, median radius) the bin
+//                 sums of eqs. (13), (14), (16) from efficiencies evaluated
+//                 once per grid radius (by mie_entries), then per (design,
+//                 wavelength) cell the same clamp / factor / matrix term as
+//                 emt_cells with f_i = f w_b.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -206,6 +212,90 @@ __global__ void emt_cells(OpticsArgs a)
         a.out_f64[3 * (size_t)c + 1] = mua;
         a.out_f64[3 * (size_t)c + 2] = g;
     }
+}
+
+__global__ void lognormal_check(LognormalArgs a)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= a.n_designs) return;
+    const int s = a.species[d], h = a.matrix[d], k = a.rmed[d];
+    const double f = a.f[d];
+    if (s < 0 || s >= a.n_species) optics_report(a.err, d, kLnErrSpecies);
+    else if (h < 0 || h >= a.n_matrix) optics_report(a.err, d, kLnErrMatrix);
+    else if (k < 0 || k >= a.n_rmed) optics_report(a.err, d, kLnErrRmed);
+    else if (!(f >= 0.0 && f <= 1.0)) optics_report(a.err, d, kLnErrFraction);
+}
+
+// one thread per (species, matrix, wavelength, median radius)
+__global__ void lognormal_table(LognormalArgs a)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t cells = (size_t)a.n_species * a.n_matrix * a.n_lambda;
+    if (t >= cells * a.n_rmed) return;
+    const int k = (int)(t % a.n_rmed);
+    const size_t c = t / a.n_rmed;
+    double ts = 0.0, ta = 0.0, tg = 0.0;
+    for (int b = 0; b < a.n_bins; ++b) {
+        const int j = k + b;
+        const double* q = a.mie + 3 * (c * a.n_radii + j);
+        const double r = a.radii[j], w = a.w[b];
+        const double ws = 1.5 * q[1] * w / (2.0 * r);
+        ts += ws;
+        ta += 1.5 * (q[0] - q[1]) * w / (2.0 * r);
+        tg += ws * q[2];
+    }
+    a.table[3 * t + 0] = ts;
+    a.table[3 * t + 1] = ta;
+    a.table[3 * t + 2] = tg;
+}
+
+// one thread per (design, wavelength) cell
+__global__ void lognormal_cells(LognormalArgs a)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)a.n_designs * a.n_lambda) return;
+    const int d = (int)(t / a.n_lambda), l = (int)(t % a.n_lambda);
+    const int s = a.species[d], h = a.matrix[d], k = a.rmed[d];
+    const double F = a.f[d];
+    const double* T = a.table + 3 * ((((size_t)s * a.n_matrix + h) * a.n_lambda + l) * a.n_rmed + k);
+    double mus = F * T[0], mua = F * T[1];
+    const double gs = F * T[2];
+    const double g = mus > 0.0 ? gs / mus : 0.0;
+    if (mus < 0.0) mus = 0.0;
+    if (mua < 0.0) mua = 0.0;
+    if (F > 0.08) {
+        const double C = 1.0 + 1.5 * F - 0.75 * F * F;
+        mus *= C;
+        mua *= C;
+    }
+    mua += 4.0 * 3.141592653589793 * a.k_m * (1.0 - F) / a.lam[l];
+    if (a.out_mu_s) a.out_mu_s[t] = (float)mus;
+    if (a.out_mu_a) a.out_mu_a[t] = (float)mua;
+    if (a.out_g) a.out_g[t] = (float)g;
+}
+
+hipError_t launch_lognormal_check(const LognormalArgs& a, hipStream_t st)
+{
+    if (a.n_designs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lognormal_check, dim3((a.n_designs + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lognormal_table(const LognormalArgs& a, hipStream_t st)
+{
+    const size_t n = (size_t)a.n_species * a.n_matrix * a.n_lambda * a.n_rmed;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(lognormal_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lognormal_cells(const LognormalArgs& a, hipStream_t st)
+{
+    const size_t n = (size_t)a.n_designs * a.n_lambda;
+    if (n == 0) return hipSuccess;
+    if ((n + 255) / 256 > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lognormal_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_optics_scan(const OpticsArgs& a, hipStream_t st)

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "fos_device.hpp"
 #include "fos_kernels.hpp"
@@ -133,6 +135,7 @@ void fos_destroy(fos_ctx* c)
         if (c->cell_of) (void)hipFree(c->cell_of);
         if (c->mie) (void)hipFree(c->mie);
         if (c->mie_scratch) (void)hipFree(c->mie_scratch);
+        if (c->ln_buf) (void)hipFree(c->ln_buf);
         if (c->tune_tallies) (void)hipFree(c->tune_tallies);
         if (c->seed_dev) (void)hipFree(c->seed_dev);
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -491,6 +494,121 @@ fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, 
     a.scratch = c->mie_scratch;
     if ((e = fos::launch_mie(a, grid, block, st)) != hipSuccess) return hip_fail(c, e, "Mie kernel");
     if ((e = fos::launch_emt(a, st)) != hipSuccess) return hip_fail(c, e, "effective-medium kernel");
+    return FOS_OK;
+}
+
+static const char* lognormal_field_name(int code)
+{
+    switch (code) {
+    case fos::kLnErrSpecies: return "species index";
+    case fos::kLnErrMatrix: return "matrix index";
+    case fos::kLnErrRmed: return "median-radius index";
+    case fos::kLnErrFraction: return "f (must be within [0, 1])";
+    default: return "unknown field";
+    }
+}
+
+fos_status fos_optics_lognormal(fos_ctx* c, const fos_lognormal_problem* p, float* mu_s, float* mu_a, float* g,
+                                void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!p) return fail(c, FOS_E_INVALID_ARG, "problem is NULL");
+    const int L = p->n_lambda, S = p->n_species, M = p->n_matrix, K = p->n_rmed, B = p->n_bins;
+    if (L < 1 || S < 1 || M < 1 || K < 1 || B < 1 || p->n_designs < 0)
+        return fail(c, FOS_E_INVALID_ARG, "n_lambda, n_species, n_matrix, n_rmed, n_bins must be >= 1, n_designs >= 0");
+    if (!p->lambda || !p->n_p || !p->k_p || !p->n_m || !p->w)
+        return fail(c, FOS_E_INVALID_ARG, "a table array pointer is NULL");
+    if (p->n_designs > 0 && (!p->species || !p->matrix || !p->rmed || !p->f))
+        return fail(c, FOS_E_INVALID_ARG, "a design array pointer is NULL");
+    if (!(p->r0 > 0.0) || !std::isfinite(p->r0) || !(p->dlnr > 0.0) || !std::isfinite(p->dlnr))
+        return fail(c, FOS_E_INVALID_ARG, "r0 and dlnr must be finite and > 0");
+    if (!(p->k_m >= 0.0) || !std::isfinite(p->k_m)) return fail(c, FOS_E_INVALID_ARG, "k_m must be finite and >= 0");
+    for (int l = 0; l < L; ++l)
+        if (!(p->lambda[l] > 0.0) || !std::isfinite(p->lambda[l]))
+            return fail(c, FOS_E_INVALID_ARG, "lambda must be finite and > 0");
+    for (int i = 0; i < S * L; ++i)
+        if (!(p->n_p[i] > 0.0) || !std::isfinite(p->n_p[i]) || !(p->k_p[i] >= 0.0) || !std::isfinite(p->k_p[i]))
+            return fail(c, FOS_E_INVALID_ARG, "particle index must have n_p > 0, k_p >= 0, finite");
+    for (int h = 0; h < M; ++h)
+        if (!(p->n_m[h] > 0.0) || !std::isfinite(p->n_m[h])) return fail(c, FOS_E_INVALID_ARG, "n_m must be finite and > 0");
+    for (int b = 0; b < B; ++b)
+        if (!(p->w[b] >= 0.0) || !std::isfinite(p->w[b])) return fail(c, FOS_E_INVALID_ARG, "w must be finite and >= 0");
+    const int J = K + B - 1;
+    const double half = 0.5 * (double)(B - 1);
+    std::vector<double> radii(J);
+    for (int j = 0; j < J; ++j) radii[j] = p->r0 * std::exp(((double)j - half) * p->dlnr);
+    if (!std::isfinite(radii[J - 1])) return fail(c, FOS_E_INVALID_ARG, "radius grid overflows");
+    // one optics cell per (species, matrix, wavelength, grid radius), one entry each
+    const size_t C = (size_t)S * M * L * J;
+    if (C > 0x7FFFFFFFull) return fail(c, FOS_E_UNSUPPORTED, "radius grid too large");
+    const size_t T = (size_t)S * M * L * K;
+    // layout of ln_buf (doubles): lam, n_m, k_m, n_p, k_p, r, f [C each], offsets [C + 1] (int64),
+    // radii [J], w [B], lambda [L], table [3 T]
+    const size_t n_dbl = 7 * C + (C + 1) + J + B + L + 3 * T;
+    std::vector<double> h(n_dbl - 3 * T);
+    double* lamc = h.data();
+    double *nmc = lamc + C, *kmc = nmc + C, *npc = kmc + C, *kpc = npc + C, *rc = kpc + C, *fc = rc + C;
+    int64_t* offc = reinterpret_cast<int64_t*>(fc + C);
+    double* rad = reinterpret_cast<double*>(offc + C + 1);
+    double *wv = rad + J, *lv = wv + B;
+    size_t e = 0;
+    for (int s = 0; s < S; ++s)
+        for (int hm = 0; hm < M; ++hm)
+            for (int l = 0; l < L; ++l)
+                for (int j = 0; j < J; ++j, ++e) {
+                    lamc[e] = p->lambda[l]; nmc[e] = p->n_m[hm]; kmc[e] = p->k_m;
+                    npc[e] = p->n_p[(size_t)s * L + l]; kpc[e] = p->k_p[(size_t)s * L + l];
+                    rc[e] = radii[j]; fc[e] = 1.0; offc[e] = (int64_t)e;
+                }
+    offc[C] = (int64_t)C;
+    std::copy(radii.begin(), radii.end(), rad);
+    std::copy(p->w, p->w + B, wv);
+    std::copy(p->lambda, p->lambda + L, lv);
+    DeviceGuard guard(c->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t err;
+    if ((err = grow(c->ln_buf, c->ln_buf_bytes, n_dbl * sizeof(double))) != hipSuccess)
+        return hip_fail(c, err, "log-normal scratch");
+    if ((err = hipMemcpyAsync(c->ln_buf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (err = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, err, "log-normal upload");
+    double* d_lamc = c->ln_buf;
+    fos_optics_problem grid{};
+    grid.n_cells = (int32_t)C;
+    grid.lam = d_lamc; grid.n_m = d_lamc + C; grid.k_m = d_lamc + 2 * C;
+    grid.n_p = d_lamc + 3 * C; grid.k_p = d_lamc + 4 * C; grid.r = d_lamc + 5 * C; grid.f = d_lamc + 6 * C;
+    grid.offsets = reinterpret_cast<const int64_t*>(d_lamc + 7 * C);
+    // efficiencies of every grid cell into c->mie (the effective-medium pass writes nothing)
+    fos_status st_mie = fos_optics_run(c, &grid, nullptr, nullptr, nullptr, nullptr, hip_stream);
+    if (st_mie != FOS_OK) return st_mie;
+    fos::LognormalArgs a{};
+    a.n_lambda = L; a.n_species = S; a.n_matrix = M; a.n_rmed = K; a.n_bins = B; a.n_radii = J;
+    a.mie = c->mie;
+    a.radii = d_lamc + 7 * C + (C + 1);
+    a.w = a.radii + J;
+    a.lam = a.w + B;
+    a.k_m = p->k_m;
+    a.table = const_cast<double*>(a.lam) + L;
+    a.n_designs = p->n_designs;
+    a.species = p->species; a.matrix = p->matrix; a.rmed = p->rmed; a.f = p->f;
+    a.err = c->err_dev;
+    a.out_mu_s = mu_s; a.out_mu_a = mu_a; a.out_g = g;
+    if ((err = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess ||
+        (err = fos::launch_lognormal_check(a, st)) != hipSuccess ||
+        (err = hipMemcpyAsync(c->err_host, c->err_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (err = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, err, "log-normal validation");
+    const unsigned long long v = *c->err_host;
+    if (v != ~0ull) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "design %llu: invalid %s", v >> 8, lognormal_field_name((int)(v & 0xFF)));
+        return fail(c, FOS_E_INVALID_ARG, buf);
+    }
+    if ((err = fos::launch_lognormal_table(a, st)) != hipSuccess || (err = fos::launch_lognormal_cells(a, st)) != hipSuccess)
+        return hip_fail(c, err, "log-normal optics");
     return FOS_OK;
 }
 

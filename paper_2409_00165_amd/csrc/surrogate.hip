@@ -19,7 +19,6 @@ using fosrt::hip_fail;
 
 namespace {
 
-constexpr int kInferRows = 65536;       // rows per member per prediction chunk
 constexpr int kColsumChunks = 64;
 
 hipError_t alloc_ws(fos_sur_state& S, void** p, size_t bytes)
@@ -49,15 +48,17 @@ hipError_t ensure_model(fos_sur_state& S)
     if ((e = hipMalloc(reinterpret_cast<void**>(&S.wb), (size_t)fos::kNets * fos::kBfParams * sizeof(__bf16))) !=
         hipSuccess)
         return e;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&S.pk), (size_t)fos::kNets * fos::kPkParams * sizeof(__bf16))) !=
+        hipSuccess)
+        return e;
     return hipMalloc(reinterpret_cast<void**>(&S.stats), 32 * sizeof(float));
 }
 
-// workspaces for `rows` rows per member (a multiple of 64); training needs
-// the saved pre-activations and gradient buffers as well
-hipError_t ensure_ws(fos_sur_state& S, int rows, bool training)
+// training workspaces for `rows` rows per member (a multiple of 64): inputs,
+// saved pre-activations and activations, logits and gradient buffers
+hipError_t ensure_ws(fos_sur_state& S, int rows)
 {
-    const bool have_train = S.dZ[0] != nullptr;
-    if (S.ws_rows >= rows && (!training || have_train)) return hipSuccess;
+    if (S.ws_rows >= rows) return hipSuccess;
     free_ws(S);
     S.xs = nullptr; S.xb = nullptr; S.ys = nullptr; S.logits = S.probs = S.loss_rows = nullptr;
     S.dlog = nullptr; S.dlog_f = nullptr; S.dW5pad = S.dW1pad = S.partial = S.step_loss = nullptr;
@@ -76,19 +77,13 @@ hipError_t ensure_ws(fos_sur_state& S, int rows, bool training)
     A(&S.loss_rows, R * sizeof(float));
     A(&S.dlog, R * fos::kPadOut * sizeof(__bf16));
     A(&S.dlog_f, R * 3 * sizeof(float));
-    if (training) {
-        for (int l = 0; l < 4; ++l) {
-            A(&S.Z[l], R * fos::kHidden * sizeof(float));
-            A(&S.H[l], R * fos::kHidden * sizeof(__bf16));
-        }
-        for (int i = 0; i < 2; ++i) {
-            A(&S.dZ[i], R * fos::kHidden * sizeof(__bf16));
-            A(&S.dZf[i], R * fos::kHidden * sizeof(float));
-        }
-    } else {
-        // prediction: two ping-pong activation buffers, no saved state
-        A(&S.H[0], R * fos::kHidden * sizeof(__bf16));
-        A(&S.H[1], R * fos::kHidden * sizeof(__bf16));
+    for (int l = 0; l < 4; ++l) {
+        A(&S.Z[l], R * fos::kHidden * sizeof(float));
+        A(&S.H[l], R * fos::kHidden * sizeof(__bf16));
+    }
+    for (int i = 0; i < 2; ++i) {
+        A(&S.dZ[i], R * fos::kHidden * sizeof(__bf16));
+        A(&S.dZf[i], R * fos::kHidden * sizeof(float));
     }
     A(&S.dW5pad, (size_t)fos::kNets * fos::kHidden * fos::kPadOut * sizeof(float));
     A(&S.dW1pad, (size_t)fos::kNets * fos::kPadIn * fos::kHidden * sizeof(float));
@@ -113,31 +108,25 @@ fos::GemmArgs gemm(int M, int N, int K, const __bf16* A, long lda, long sA, cons
     return g;
 }
 
-// Forward through the 4 hidden layers and the logits for `rows_pad` rows per
-// member whose standardised features are in S.xs.  With `training` the
+// Training forward through the 4 hidden layers and the logits for `rows_pad`
+// rows per member whose standardised features are in S.xs; the
 // pre-activations Z1..Z4 and activations H1..H4 are kept for the backward
-// pass; otherwise H ping-pongs between two buffers.  Returns the buffer of
-// the last hidden activations in *h_last.
-hipError_t forward(fos_sur_state& S, int rows_pad, bool training, hipStream_t st)
+// pass.  (Prediction uses the fused kernel of mlp_infer.hip instead.)
+hipError_t forward(fos_sur_state& S, int rows_pad, hipStream_t st)
 {
     const long RH = (long)rows_pad * fos::kHidden;
     const long PS = (long)fos::kParams, BS = (long)fos::kBfParams;
-    hipError_t e = fos::launch_first_layer(rows_pad, S.xs, S.params, fos::kParams, training ? S.Z[0] : nullptr,
-                                           S.H[0], fos::kNets, st);
+    hipError_t e = fos::launch_first_layer(rows_pad, S.xs, S.params, fos::kParams, S.Z[0], S.H[0], fos::kNets, st);
     if (e != hipSuccess) return e;
     const size_t wof[3] = {fos::kBfW2, fos::kBfW3, fos::kBfW4};
     const size_t bof[3] = {fos::kOffB2, fos::kOffB3, fos::kOffB4};
-    __bf16* h_in = S.H[0];
     for (int l = 0; l < 3; ++l) {
-        __bf16* h_out = training ? S.H[l + 1] : S.H[(l + 1) & 1];
-        float* z_out = training ? S.Z[l + 1] : nullptr;
-        fos::GemmArgs g = gemm(rows_pad, fos::kHidden, fos::kHidden, h_in, fos::kHidden, RH, S.wb + wof[l],
-                               fos::kHidden, BS, z_out, fos::kHidden, RH, h_out, RH, S.params + bof[l], PS,
+        fos::GemmArgs g = gemm(rows_pad, fos::kHidden, fos::kHidden, S.H[l], fos::kHidden, RH, S.wb + wof[l],
+                               fos::kHidden, BS, S.Z[l + 1], fos::kHidden, RH, S.H[l + 1], RH, S.params + bof[l], PS,
                                nullptr, 0);
         if ((e = fos::launch_gemm(g, false, false, fos::kEpiBiasGelu, fos::kNets, st)) != hipSuccess) return e;
-        h_in = h_out;
     }
-    fos::GemmArgs g = gemm(rows_pad, fos::kPadOut, fos::kHidden, h_in, fos::kHidden, RH, S.wb + fos::kBfW5p,
+    fos::GemmArgs g = gemm(rows_pad, fos::kPadOut, fos::kHidden, S.H[3], fos::kHidden, RH, S.wb + fos::kBfW5p,
                            fos::kPadOut, BS, S.logits, fos::kPadOut, (long)rows_pad * fos::kPadOut, nullptr, 0,
                            nullptr, 0, nullptr, 0);
     return fos::launch_gemm(g, false, false, fos::kEpiStore, fos::kNets, st);
@@ -231,6 +220,10 @@ static void free_sweep(fos_sur_state& S)
     for (void* p : S.sweep) (void)hipFree(p);
     S.sweep.clear();
     S.sweep_cap = 0;
+    for (void* p : S.sub) (void)hipFree(p);
+    S.sub.clear();
+    S.sub_cap = 0;
+    S.sub_layers = 0;
 }
 
 void fos_sur_free(fos_sur_state& S)
@@ -241,6 +234,7 @@ void fos_sur_free(fos_sur_state& S)
     for (float* p : {S.params, S.m, S.v, S.grads, S.stats})
         if (p) (void)hipFree(p);
     if (S.wb) (void)hipFree(S.wb);
+    if (S.pk) (void)hipFree(S.pk);
     if (S.perm) (void)hipFree(S.perm);
     S = fos_sur_state();
 }
@@ -284,7 +278,7 @@ fos_status fos_sur_train(fos_ctx* c, const float* x, const float* y, int64_t n, 
     hipError_t e;
     if ((e = ensure_model(S)) != hipSuccess) return hip_fail(c, e, "model buffers");
     const int B = o->batch;
-    if ((e = ensure_ws(S, B, true)) != hipSuccess) return hip_fail(c, e, "training workspace");
+    if ((e = ensure_ws(S, B)) != hipSuccess) return hip_fail(c, e, "training workspace");
     const int64_t steps_per_epoch = n / B;
     // per-epoch, per-member affine shuffles i -> (a i + b) mod n, gcd(a, n) = 1
     std::mt19937_64 rng(o->seed ^ 0x5EEDF05ull);
@@ -335,7 +329,7 @@ fos_status fos_sur_train(fos_ctx* c, const float* x, const float* y, int64_t n, 
         for (int64_t s = 0; s < steps_per_epoch; ++s, ++step) {
             fos::StdArgs sa = std_args(S, x, y, n, s * B, B, B, pm);
             if ((e = fos::launch_standardize(sa, fos::kNets, st)) != hipSuccess) return hip_fail(c, e, "gather");
-            if ((e = forward(S, B, true, st)) != hipSuccess) return hip_fail(c, e, "forward");
+            if ((e = forward(S, B, st)) != hipSuccess) return hip_fail(c, e, "forward");
             if ((e = softmax(S, B, B, true, st)) != hipSuccess) return hip_fail(c, e, "softmax");
             if ((e = backward(S, B, st)) != hipSuccess) return hip_fail(c, e, "backward");
             const double frac = total > 1 ? (double)step / (double)(total - 1) : 1.0;
@@ -374,26 +368,14 @@ fos_status fos_sur_predict(fos_ctx* c, const float* x, const uint8_t* eligible, 
     if (!x) return fail(c, FOS_E_INVALID_ARG, "x is NULL");
     DeviceGuard guard(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    const int chunk = (int)std::min<int64_t>(kInferRows, ((n + 63) / 64) * 64);
-    hipError_t e = ensure_ws(S, chunk, false);
-    if (e != hipSuccess) return hip_fail(c, e, "prediction workspace");
-    for (int64_t b = 0; b < n; b += chunk) {
-        const int rows = (int)std::min<int64_t>(chunk, n - b);
-        const int rows_pad = ((rows + 63) / 64) * 64;
-        fos::StdArgs sa = std_args(S, x, nullptr, n, b, rows_pad, rows_pad, nullptr);
-        sa.xb = nullptr;
-        if ((e = fos::launch_standardize(sa, fos::kNets, st)) != hipSuccess) return hip_fail(c, e, "standardize");
-        if ((e = forward(S, rows_pad, false, st)) != hipSuccess) return hip_fail(c, e, "forward");
-        if ((e = softmax(S, rows, rows_pad, false, st)) != hipSuccess) return hip_fail(c, e, "softmax");
-        fos::GateArgs ga{};
-        ga.rows = rows; ga.rows_pad = rows_pad; ga.nets = fos::kNets;
-        ga.out_offset = b; ga.n_total = n;
-        ga.probs = S.probs; ga.x = x + (size_t)b * fos::kFeatures;
-        ga.eligible = eligible ? eligible + b : nullptr;
-        ga.lo = S.stats + 2 * fos::kFeatures; ga.hi = S.stats + 3 * fos::kFeatures;
-        ga.rat = rat; ga.spread = spread; ga.in_domain = in_domain; ga.members = members;
-        if ((e = fos::launch_ensemble_gate(ga, st)) != hipSuccess) return hip_fail(c, e, "gate");
-    }
+    // fragment-ordered weights from the current masters, then one fused launch
+    // (network of every member + gate) over all rows
+    hipError_t e = fos::launch_pack_infer(S.params, S.pk, fos::kNets, st);
+    if (e != hipSuccess) return hip_fail(c, e, "inference weights");
+    fos::InferArgs ia{};
+    ia.n = n; ia.x = x; ia.eligible = eligible; ia.stats = S.stats; ia.params = S.params; ia.pk = S.pk;
+    ia.rat = rat; ia.spread = spread; ia.in_domain = in_domain; ia.members = members;
+    if ((e = fos::launch_mlp_infer(ia, st)) != hipSuccess) return hip_fail(c, e, "inference");
     return FOS_OK;
 }
 
@@ -408,12 +390,12 @@ fos_status fos_sur_grad(fos_ctx* c, const float* x, const float* y, int64_t n, f
     if (!x || !y || !grads) return fail(c, FOS_E_INVALID_ARG, "NULL array");
     DeviceGuard guard(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    hipError_t e = ensure_ws(S, (int)n, true);
+    hipError_t e = ensure_ws(S, (int)n);
     if (e != hipSuccess) return hip_fail(c, e, "workspace");
     const int R = (int)n;
     fos::StdArgs sa = std_args(S, x, y, n, 0, R, R, nullptr);
     if ((e = fos::launch_standardize(sa, fos::kNets, st)) != hipSuccess ||
-        (e = forward(S, R, true, st)) != hipSuccess || (e = softmax(S, R, R, true, st)) != hipSuccess ||
+        (e = forward(S, R, st)) != hipSuccess || (e = softmax(S, R, R, true, st)) != hipSuccess ||
         (e = backward(S, R, st)) != hipSuccess)
         return hip_fail(c, e, "gradient");
     if ((e = hipMemcpyAsync(grads, S.grads, (size_t)fos::kNets * fos::kParams * sizeof(float),
@@ -429,14 +411,17 @@ fos_status fos_sur_grad(fos_ctx* c, const float* x, const float* y, int64_t n, f
     return FOS_OK;
 }
 
-static hipError_t ensure_sweep(fos_sur_state& S, int64_t n, int L)
+// per-item sweep scratch for n items (features, flags, compaction)
+static hipError_t ensure_sweep(fos_sur_state& S, int64_t n)
 {
     if (!S.total_host) {
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&S.total_host), sizeof(unsigned long long));
         if (e != hipSuccess) return e;
     }
-    if (S.sweep_cap >= n && S.sweep_layers >= L) return hipSuccess;
-    free_sweep(S);
+    if (S.sweep_cap >= n) return hipSuccess;
+    for (void* p : S.sweep) (void)hipFree(p);
+    S.sweep.clear();
+    S.sweep_cap = 0;
     hipError_t e = hipSuccess;
     auto A = [&](void* pp, size_t bytes) {
         if (e != hipSuccess) return;
@@ -453,12 +438,31 @@ static hipError_t ensure_sweep(fos_sur_state& S, int64_t n, int L)
     A(&S.sblock, 2 * (blocks + 1) * sizeof(unsigned long long));
     A(&S.sidx, N * sizeof(int64_t));
     A(&S.stotal, sizeof(unsigned long long));
-    A(&S.sub_nl, N * sizeof(int32_t));
-    for (int k = 0; k < 5; ++k) A(&S.sub_l[k], N * L * sizeof(float));
-    for (int k = 0; k < 4; ++k) A(&S.sub_i[k], N * sizeof(float));
-    A(&S.sub_ph, N * sizeof(uint64_t));
-    A(&S.sub_tal, N * 6 * sizeof(unsigned long long));
-    if (e == hipSuccess) { S.sweep_cap = n; S.sweep_layers = L; }
+    if (e == hipSuccess) S.sweep_cap = n;
+    return e;
+}
+
+// the gathered fallback sub-problem, sized by the fallback count m
+static hipError_t ensure_sub(fos_sur_state& S, int64_t m, int L)
+{
+    if (S.sub_cap >= m && S.sub_layers >= L) return hipSuccess;
+    for (void* p : S.sub) (void)hipFree(p);
+    S.sub.clear();
+    S.sub_cap = 0;
+    hipError_t e = hipSuccess;
+    auto A = [&](void* pp, size_t bytes) {
+        if (e != hipSuccess) return;
+        void** p = reinterpret_cast<void**>(pp);
+        e = hipMalloc(p, std::max<size_t>(bytes, 256));
+        if (e == hipSuccess) S.sub.push_back(*p);
+    };
+    const size_t M = (size_t)m;
+    A(&S.sub_nl, M * sizeof(int32_t));
+    for (int k = 0; k < 5; ++k) A(&S.sub_l[k], M * L * sizeof(float));
+    for (int k = 0; k < 4; ++k) A(&S.sub_i[k], M * sizeof(float));
+    A(&S.sub_ph, M * sizeof(uint64_t));
+    A(&S.sub_tal, M * 6 * sizeof(unsigned long long));
+    if (e == hipSuccess) { S.sub_cap = m; S.sub_layers = L; }
     return e;
 }
 
@@ -480,7 +484,7 @@ fos_status fos_sweep_run(fos_ctx* c, const fos_mc_problem* p, float spread_max, 
     if (n == 0) return FOS_OK;
     DeviceGuard guard(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    hipError_t e = ensure_sweep(S, n, p->max_layers);
+    hipError_t e = ensure_sweep(S, n);
     if (e != hipSuccess) return hip_fail(c, e, "sweep scratch");
     fos_status s = fos_sur_features(c, p, S.sx, S.selig, hip_stream);
     if (s != FOS_OK) return s;
@@ -500,6 +504,8 @@ fos_status fos_sweep_run(fos_ctx* c, const fos_mc_problem* p, float spread_max, 
     const int64_t m = (int64_t)*S.total_host;
     if (n_fallback) *n_fallback = m;
     if (m == 0) return FOS_OK;
+    if (m > 0x7FFFFFFF) return fail(c, FOS_E_UNSUPPORTED, "more than 2^31-1 fallback items");
+    if ((e = ensure_sub(S, m, p->max_layers)) != hipSuccess) return hip_fail(c, e, "fallback sub-problem");
     fos::GatherArgs ga{};
     ga.m = m; ga.L = p->max_layers; ga.idx = S.sidx;
     ga.n_layers = p->n_layers; ga.mu_s = p->mu_s; ga.mu_a = p->mu_a; ga.g = p->g; ga.n_layer = p->n_layer;
@@ -511,7 +517,6 @@ fos_status fos_sweep_run(fos_ctx* c, const fos_mc_problem* p, float spread_max, 
     ga.o_n_upper = S.sub_i[0]; ga.o_n_lower = S.sub_i[1]; ga.o_k_lower = S.sub_i[2]; ga.o_mu0 = S.sub_i[3];
     ga.o_photons = S.sub_ph; ga.photons = fallback_photons;
     if ((e = fos::launch_gather_items(ga, st)) != hipSuccess) return hip_fail(c, e, "fallback gather");
-    if (m > 0x7FFFFFFF) return fail(c, FOS_E_UNSUPPORTED, "more than 2^31-1 fallback items");
     fos_mc_problem sub{};
     sub.n_items = (int32_t)m; sub.max_layers = p->max_layers; sub.n_layers = S.sub_nl;
     sub.mu_s = S.sub_l[0]; sub.mu_a = S.sub_l[1]; sub.g = S.sub_l[2]; sub.n_layer = S.sub_l[3];

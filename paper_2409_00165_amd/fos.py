@@ -42,6 +42,14 @@ class fos_optics_problem(Structure):
                 ("f", c_void_p)]
 
 
+class fos_lognormal_problem(Structure):
+    _fields_ = [("n_lambda", c_int32), ("lam", c_void_p), ("n_species", c_int32), ("n_p", c_void_p),
+                ("k_p", c_void_p), ("n_matrix", c_int32), ("n_m", c_void_p), ("k_m", ctypes.c_double),
+                ("r0", ctypes.c_double), ("dlnr", ctypes.c_double), ("n_rmed", c_int32), ("n_bins", c_int32),
+                ("w", c_void_p), ("n_designs", c_int32), ("species", c_void_p), ("matrix", c_void_p),
+                ("rmed", c_void_p), ("f", c_void_p)]
+
+
 class fos_train_opts(Structure):
     _fields_ = [("epochs", c_int32), ("batch", c_int32), ("lr", c_float), ("lr_min", c_float),
                 ("seed", c_uint64), ("resume", c_int32), ("loss_history", c_void_p)]
@@ -118,6 +126,9 @@ def lib():
         L.fos_optics_run.argtypes = [c_void_p, POINTER(fos_optics_problem), c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]
         L.fos_optics_run.restype = c_int
+        L.fos_optics_lognormal.argtypes = [c_void_p, POINTER(fos_lognormal_problem), c_void_p, c_void_p, c_void_p,
+                                           c_void_p]
+        L.fos_optics_lognormal.restype = c_int
         L.fos_philox_words.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p,
                                        c_void_p]
         L.fos_philox_words.restype = c_int
@@ -322,6 +333,39 @@ class OpticsProblem:
         import torch
         t = lambda k, dt=np.float64: torch.from_numpy(np.ascontiguousarray(req[k], dtype=dt)).to(device)
         return cls(t("lam"), t("n_m"), t("k_m"), t("offsets", np.int64), t("n_p"), t("k_p"), t("r"), t("f"))
+
+
+class LognormalProblem:
+    """One fos_lognormal_problem: the grid tables as host float64 arrays (kept
+    alive here) and the per-design arrays as device tensors."""
+
+    def __init__(self, lam, n_p, k_p, n_m, k_m, r0, dlnr, n_rmed, w, species, matrix, rmed, f):
+        import numpy as np
+        import torch
+        h = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        self.host = dict(lam=h(lam), n_p=h(n_p), k_p=h(k_p), n_m=h(n_m), w=h(w))
+        self.tensors = dict(species=species, matrix=matrix, rmed=rmed, f=f)
+        L = self.host["lam"].size
+        S = self.host["n_p"].size // L
+        D = species.numel()
+        s = fos_lognormal_problem()
+        s.n_lambda, s.n_species, s.n_matrix = L, S, self.host["n_m"].size
+        s.lam, s.n_p, s.k_p = (self.host[k].ctypes.data for k in ("lam", "n_p", "k_p"))
+        s.n_m, s.w = self.host["n_m"].ctypes.data, self.host["w"].ctypes.data
+        s.k_m, s.r0, s.dlnr, s.n_rmed, s.n_bins = float(k_m), float(r0), float(dlnr), int(n_rmed), self.host["w"].size
+        s.n_designs = D
+        for k in ("species", "matrix", "rmed"):
+            setattr(s, k, _ptr(self.tensors[k], torch.int32, D))
+        s.f = _ptr(f, torch.float64, D)
+        self.n_lambda, self.n_designs, self.struct = L, D, s
+
+
+def fos_optics_lognormal(ctx, problem: LognormalProblem, mu_s=None, mu_a=None, g=None, stream=None) -> None:
+    import torch
+    C = problem.n_designs * problem.n_lambda
+    _check(ctx, lib().fos_optics_lognormal(ctx, ctypes.byref(problem.struct), _ptr(mu_s, torch.float32, C),
+                                           _ptr(mu_a, torch.float32, C), _ptr(g, torch.float32, C),
+                                           _stream(stream)))
 
 
 def fos_optics_run(ctx, problem: OpticsProblem, mu_s=None, mu_a=None, g=None, out_f64=None,

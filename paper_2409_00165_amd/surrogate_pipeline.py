@@ -45,6 +45,42 @@ def optics_problem(ctx, wl, device="cuda"):
                          t(geo["n_lower"], np.float32), t(geo["k_lower"], np.float32), t(geo["mu0"], np.float32), ph)
 
 
+def paint_problem(ctx, sweep, device="cuda"):
+    """Transport problem of a PaintSweep: the optics of every (design,
+    wavelength) cell by fos_optics_lognormal, the other per-item arrays by
+    repeating each design's values over its wavelengths."""
+    import torch
+    D, L = sweep.n_designs, len(sweep.wavelengths)
+    n = D * L
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    lp = fos.LognormalProblem(**sweep.lognormal_tables(), species=dev(sweep.species, np.int32),
+                              matrix=dev(sweep.matrix, np.int32), rmed=dev(sweep.rmed, np.int32),
+                              f=dev(sweep.f, np.float64))
+    mus, mua, g = (torch.empty(n, dtype=torch.float32, device=device) for _ in range(3))
+    fos.fos_optics_lognormal(ctx, lp, mus, mua, g)
+    per_item = lambda a: dev(a, np.float32).repeat_interleave(L)
+    ph = torch.full((n,), sweep.photons, dtype=torch.int64, device=device)
+    if hasattr(torch, "uint64"):
+        ph = ph.view(torch.uint64)
+    ones = torch.ones(n, dtype=torch.float32, device=device)
+    return fos.MCProblem(torch.ones(n, dtype=torch.int32, device=device), mus, mua, g,
+                         per_item(W.PAINT_NM[sweep.matrix]), per_item(sweep.thickness), ones, ones.clone(),
+                         torch.zeros(n, dtype=torch.float32, device=device), ones.clone(), ph)
+
+
+def take_items(prob, idx):
+    """The sub-problem of the items `idx` (device int64 tensor), in that order."""
+    import torch
+    T = prob.tensors
+    L = prob.max_layers
+    rows = lambda t: t.view(prob.n_items, L)[idx].reshape(-1).contiguous()
+    ph = T["photons"].view(torch.int64)[idx].contiguous().view(T["photons"].dtype)
+    return fos.MCProblem(T["n_layers"][idx].contiguous(), rows(T["mu_s"]), rows(T["mu_a"]), rows(T["g"]),
+                         rows(T["n_layer"]), rows(T["thickness"]), T["n_upper"][idx].contiguous(),
+                         T["n_lower"][idx].contiguous(), T["k_lower"][idx].contiguous(), T["mu0"][idx].contiguous(),
+                         ph)
+
+
 def with_photons(prob, photons: int):
     """The same problem with every item's photon budget replaced."""
     import torch
@@ -66,6 +102,18 @@ def mc_fractions(ctx, prob, seed: int):
     fos.fos_mc_fractions(ctx, tal, rat)
     steps = int(tal.view(n, fos.N_TALLY)[:, 5].sum().item())
     return rat, steps
+
+
+def training_recipe_id(seed: int) -> str:
+    """Fingerprint of the training-item recipe (the first 1000 items drawn
+    from `seed`): stored with saved labels, so labels are never re-joined to
+    features drawn by a different recipe."""
+    import hashlib
+    a = W.surrogate_training_items(1000, seed)
+    h = hashlib.sha1()
+    for k in sorted(a):
+        h.update(np.ascontiguousarray(a[k]).tobytes())
+    return h.hexdigest()[:16]
 
 
 def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000, log=None, label: bool = True):

@@ -203,22 +203,87 @@ def stacks_3layer(n_designs: int = 4096, n_lambda: int = 100, seed: int = 202409
     return Workload("stacks_3layer", lam, designs)
 
 
+# Paint designs put the median radius and the matrix index on grids, so that
+# every size bin of every design is one of a few dozen radii: the bins of
+# lognormal_bins() are PAINT_DLNR wide in ln r, and the medians are spaced by
+# the same step, so bin b of the median with index k is grid radius k + b.
+# The Mie efficiencies are then evaluated once per grid radius, which is what
+# makes a sweep of 10^6 designs affordable (fos_optics_lognormal).
+PAINT_SIGMA_LN = 0.3
+PAINT_BINS = 20
+PAINT_DLNR = 2.0 * 3.0 * PAINT_SIGMA_LN / PAINT_BINS          # 0.09
+PAINT_R0 = 0.05                                                # smallest median, um
+PAINT_N_RMED = int(math.floor(math.log(1.0 / PAINT_R0) / PAINT_DLNR)) + 1   # medians up to 1 um
+PAINT_NM = np.linspace(1.3, 1.7, 9)                            # matrix indices
+PAINT_KM = 1e-4
+PAINT_SPECIES = ("A", "B")
+
+
+@dataclass
+class PaintSweep:
+    """Single-layer paint designs in air at normal incidence, as flat arrays.
+    Design d: species PAINT_SPECIES[species[d]], matrix PAINT_NM[matrix[d]] +
+    i PAINT_KM, log-normal radii with median PAINT_R0 exp(rmed[d] PAINT_DLNR)
+    (sigma_ln 0.3, 20 bins), total volume fraction f[d], thickness[d] um."""
+
+    wavelengths: np.ndarray
+    species: np.ndarray
+    matrix: np.ndarray
+    rmed: np.ndarray
+    f: np.ndarray
+    thickness: np.ndarray
+    photons: int
+
+    @property
+    def n_designs(self) -> int:
+        return len(self.f)
+
+    @property
+    def r_med(self) -> np.ndarray:
+        return PAINT_R0 * np.exp(self.rmed * PAINT_DLNR)
+
+    def workload(self, designs=None) -> Workload:
+        """The same designs as a Workload (particle lists per layer)."""
+        idx = range(self.n_designs) if designs is None else designs
+        out = []
+        for d in idx:
+            r, w = lognormal_bins(float(self.r_med[d]), PAINT_SIGMA_LN, PAINT_BINS)
+            pop = Particles(PAINT_SPECIES[int(self.species[d])], r, float(self.f[d]) * w)
+            lay = Layer(float(self.thickness[d]), float(PAINT_NM[int(self.matrix[d])]), PAINT_KM, [pop])
+            out.append(Design([lay], photons=self.photons))
+        return Workload("paint_1layer", self.wavelengths, out)
+
+    def lognormal_tables(self) -> dict:
+        """Grid description for fos_optics_lognormal (host arrays)."""
+        lam = self.wavelengths
+        n_p = np.stack([SPECIES[s](lam)[0] for s in PAINT_SPECIES])
+        k_p = np.stack([SPECIES[s](lam)[1] for s in PAINT_SPECIES])
+        _, w = lognormal_bins(1.0, PAINT_SIGMA_LN, PAINT_BINS)
+        return {"lam": lam, "n_p": n_p, "k_p": k_p, "n_m": PAINT_NM, "k_m": PAINT_KM, "r0": PAINT_R0,
+                "dlnr": PAINT_DLNR, "n_rmed": PAINT_N_RMED, "w": w}
+
+
+def paint_sweep(n_designs: int, n_lambda: int = 200, seed: int = 20240901, photons: int = 100_000) -> PaintSweep:
+    """The per-layer distribution of ``stacks_3layer`` with one layer (t ~
+    U[5, 500] um, f ~ U[0.01, 0.3], median ~ U[0.05, 1] um, species A or B,
+    n_m ~ U[1.3, 1.7]), median and n_m snapped to their grids."""
+    rng = np.random.default_rng(seed)
+    n = n_designs
+    t = rng.uniform(5.0, 500.0, n)
+    f = rng.uniform(0.01, 0.3, n)
+    rm = rng.uniform(0.05, 1.0, n)
+    sp = (rng.uniform(size=n) >= 0.5).astype(np.int32)
+    nm = rng.uniform(1.3, 1.7, n)
+    rmed = np.clip(np.rint(np.log(rm / PAINT_R0) / PAINT_DLNR), 0, PAINT_N_RMED - 1).astype(np.int32)
+    mat = np.clip(np.rint((nm - PAINT_NM[0]) / (PAINT_NM[1] - PAINT_NM[0])), 0, len(PAINT_NM) - 1).astype(np.int32)
+    return PaintSweep(grid_log(0.3, 16.0, n_lambda), sp, mat, rmed, f, t, photons)
+
+
 def paint_1layer(n_designs: int, n_lambda: int = 200, seed: int = 20240901,
                  photons: int = 100_000) -> Workload:
-    """Single-layer paint designs in air (the surrogate's domain): the
-    per-layer distribution of ``stacks_3layer`` with one layer."""
-    rng = np.random.default_rng(seed)
-    lam = grid_log(0.3, 16.0, n_lambda)
-    designs = []
-    for _ in range(n_designs):
-        t = rng.uniform(5.0, 500.0)
-        f = rng.uniform(0.01, 0.3)
-        rm = rng.uniform(0.05, 1.0)
-        sp = "A" if rng.uniform() < 0.5 else "B"
-        nm = rng.uniform(1.3, 1.7)
-        r, w = lognormal_bins(rm, 0.3, 20)
-        designs.append(Design([Layer(t, nm, 1e-4, [Particles(sp, r, f * w)])], photons=photons))
-    return Workload("paint_1layer", lam, designs)
+    """Single-layer paint designs in air (the surrogate's domain) as a
+    Workload; the designs of paint_sweep() with the same arguments."""
+    return paint_sweep(n_designs, n_lambda, seed, photons).workload()
 
 
 # ----------------------------------------------------------------------------
@@ -316,18 +381,23 @@ def optics_request(wl: Workload):
 # ----------------------------------------------------------------------------
 
 # Box of the training inputs, covering the optical depths and asymmetries of
-# the two-species and three-layer workloads (their optics span tau_s 1e-8 ..
-# 3.2e3, tau_a 5e-4 .. 1.2e2, g 0 .. 0.995).
-TRAIN_TAU_S = (1e-7, 5e3)
+# the two-species, three-layer and single-layer paint workloads (their optics
+# span tau_s 0 .. 1.25e4, tau_a 4e-4 .. 1.4e2, g 0 .. 0.995; tau_s ~ 0 where a
+# species is index-matched to its matrix).
+TRAIN_TAU_S = (1e-9, 1.5e4)
+TRAIN_TAU_S_ZERO = 0.02      # share of samples without scattering
+TRAIN_N_M = (1.28, 1.72)
 TRAIN_TAU_A = (1e-4, 3e2)
 TRAIN_G = (-0.1, 0.999)
 
 
 def surrogate_training_items(n: int, seed: int, photons: int = 100_000, thickness: float = 100.0):
-    """Single-layer items for Monte Carlo labels: tau_s and tau_a log-uniform
-    over the box above; g uniform over TRAIN_G for half the items, else with
+    """Single-layer items for Monte Carlo labels: tau_s log-uniform over the
+    box above (a share TRAIN_TAU_S_ZERO without scattering), tau_a
+    log-uniform; g uniform over TRAIN_G for half the items, else with
     1 - g log-uniform over the same range (the forward-peaked end, where the
-    transport follows tau_s (1 - g), gets its share); matrix n ~ U[1.3, 1.7];
+    transport follows tau_s (1 - g), gets its share); matrix n uniform over
+    TRAIN_N_M (a little wider than the workloads' 1.3 .. 1.7);
     substrate n ~ U[1, 3.5] (half exactly 1, air); k = 0 for half else
     log-U[1e-3, 1e-1]; incidence cosine ~ U[0.5, 1] (half exactly 1); air
     above.  The exact air / normal-incidence values are the ones the
@@ -335,11 +405,11 @@ def surrogate_training_items(n: int, seed: int, photons: int = 100_000, thicknes
     Returns numpy arrays shaped like item_geometry() plus mu_s, mu_a, g."""
     rng = np.random.default_rng(seed)
     lu = lambda lo, hi: np.exp(rng.uniform(math.log(lo), math.log(hi), n))
-    tau_s = lu(*TRAIN_TAU_S)
+    tau_s = np.where(rng.uniform(size=n) < TRAIN_TAU_S_ZERO, 0.0, lu(*TRAIN_TAU_S))
     tau_a = lu(*TRAIN_TAU_A)
     g = np.where(rng.uniform(size=n) < 0.5, rng.uniform(*TRAIN_G, n),
                  1.0 - lu(1.0 - TRAIN_G[1], 1.0 - TRAIN_G[0]))
-    n_m = rng.uniform(1.3, 1.7, n)
+    n_m = rng.uniform(*TRAIN_N_M, n)
     n_sub = np.where(rng.uniform(size=n) < 0.5, 1.0, rng.uniform(1.0, 3.5, n))
     k_sub = np.where(rng.uniform(size=n) < 0.5, 0.0, lu(1e-3, 1e-1))
     mu0 = np.where(rng.uniform(size=n) < 0.5, 1.0, rng.uniform(0.5, 1.0, n))

@@ -133,6 +133,44 @@ def test_forward_members_match_oracle(ctx, torch):
     assert np.allclose(spread.cpu().numpy(), (mem.max(0) - mem.min(0)).max(1), atol=1e-6)
 
 
+def test_prediction_spans_many_tiles_row_independently(ctx, torch):
+    """200,003 rows (1,563 workgroups of 128, ragged last tile): rows predicted
+    in a small call are bit-identical inside the large call (head and tail),
+    and sampled rows match the bf16-emulating oracle."""
+    from paper_2409_00165_amd import fos
+    members, mean, std, lo, hi = _model(5)
+    fos.fos_sur_load(ctx, _blob(members, mean, std, lo, hi))
+    n = 200_003
+    x = _features(n, 11, mean, std)
+    dx = torch.from_numpy(x).cuda()
+
+    def run(xx):
+        m = xx.shape[0]
+        out = (torch.zeros(m * 3, device="cuda"), torch.zeros(m, device="cuda"),
+               torch.zeros(m, dtype=torch.uint8, device="cuda"), torch.zeros(4 * m * 3, device="cuda"))
+        fos.fos_sur_predict(ctx, xx.reshape(-1), rat=out[0], spread=out[1], in_domain=out[2], members=out[3])
+        return out
+
+    big = run(dx)
+    head = run(dx[:1000].contiguous())
+    tail = run(dx[-77:].contiguous())
+    torch.cuda.synchronize()
+    bm = big[3].view(4, n, 3)
+    assert torch.equal(big[0].view(n, 3)[:1000], head[0].view(1000, 3))
+    assert torch.equal(big[1][:1000], head[1]) and torch.equal(big[2][:1000], head[2])
+    assert torch.equal(bm[:, :1000], head[3].view(4, 1000, 3))
+    assert torch.equal(big[0].view(n, 3)[-77:], tail[0].view(77, 3))
+    assert torch.equal(bm[:, -77:], tail[3].view(4, 77, 3))
+    rows = np.random.default_rng(12).choice(n, size=300, replace=False)
+    xs = ((x[rows].astype(np.float64) - mean) / std).astype(np.float32).astype(np.float64)
+    got = bm[:, torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for m in range(4):
+        worst = max(worst, np.abs(got[m] - _emulated_forward(_as_gpu_weights(members[m]), xs)).max())
+    print("sampled rows of the 200,003-row call vs bf16-emulating oracle:", worst, flush=True)
+    assert worst < 5e-3
+
+
 def test_gate_domain_and_eligibility(ctx, torch):
     from paper_2409_00165_amd import fos
     members, mean, std, lo, hi = _model(1)

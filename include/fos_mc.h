@@ -180,6 +180,35 @@ fos_status fos_mc_graph_launch(fos_ctx* ctx, uint64_t seed, void* hip_stream);
  * [n * 3].  Asynchronous. */
 fos_status fos_mc_fractions(fos_ctx* ctx, int32_t n, const uint64_t* tallies, float* rat, void* hip_stream);
 
+/* Weighted-packet walk: the variance-reduction form of the walk in MCML
+ * (ref. [45], which the paper's Monte Carlo follows, Methodology, Photon
+ * transport).  Same problem, launch, counter-based random numbers and
+ * boundaries as fos_mc_execute, but each photon is a packet of weight W:
+ * it enters with W = 1 - R0 (the specular part R0 is tallied as weight, no
+ * draw); at each interaction it deposits W mu_a/mu_t and always scatters; it
+ * leaves through a face with its whole weight (all-or-none Fresnel decision
+ * as in the analog walk); below a weight of 1e-4 it survives a roulette with
+ * probability 0.1 and ten times the weight.  Estimates are unbiased;
+ * R + A + T = 1 holds in expectation.  tallies DEVICE uint64
+ * [n_items * FOS_N_TALLY_W]: specular R, diffuse R, A, T, and the sums of
+ * squares of each photon's diffuse-R, A and T totals, all in units of 2^-36
+ * of a photon's weight (integer sums: results are bit-identical for any
+ * launch), then roulette ends, capped photons, photon-steps and photons.  An
+ * item must not exceed 2^27 photons.  Asynchronous, allocates nothing. */
+#define FOS_N_TALLY_W 11
+fos_status fos_mc_execute_weighted(fos_ctx* ctx, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies,
+                                   void* hip_stream);
+
+/* fos_mc_prepare + fos_mc_execute_weighted. */
+fos_status fos_mc_run_weighted(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
+                               const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
+
+/* (R, A, T) means from weighted tallies, rat DEVICE float [n * 3], and the
+ * standard errors of those estimates from the per-photon sums of squares, se
+ * DEVICE float [n * 3] (may be NULL).  Asynchronous. */
+fos_status fos_mc_weighted_fractions(fos_ctx* ctx, int32_t n, const uint64_t* tallies, float* rat, float* se,
+                                     void* hip_stream);
+
 /* Number of items of the prepared problem (0 if none). */
 int32_t fos_mc_prepared_items(const fos_ctx* ctx);
 

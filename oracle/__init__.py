@@ -62,6 +62,9 @@ def _load():
         lib.orc_walk_batch.argtypes = [c_int, c_int, POINTER(c_int32), d, d, d, d, d, d, d, d, d,
                                        u64p, POINTER(c_uint32), c_uint64, c_uint64, c_int, u64p]
         lib.orc_walk_batch.restype = c_int
+        lib.orc_walk_weighted_batch.argtypes = [c_int, c_int, POINTER(c_int32), d, d, d, d, d, d, d, d, d,
+                                                u64p, POINTER(c_uint32), c_uint64, c_uint64, c_int, d, u64p]
+        lib.orc_walk_weighted_batch.restype = c_int
         lib.orc_mie_coeffs.argtypes = [c_double, c_double, c_double, c_double, c_int, d, d]
         lib.orc_mie_nmax.argtypes = [c_double]
         lib.orc_mie_nmax.restype = c_int
@@ -156,6 +159,34 @@ def walk_batch(n_layers, mu_s, mu_a, g, n_layer, thickness, n_upper, n_lower, k_
     if rc != 0:
         raise ValueError("orc_walk_batch rejected its arguments")
     return out
+
+
+N_WTALLY = 8   # specular R, diffuse R, A, T, sums of squares of diffuse R, A, T, roulette ends
+
+
+def walk_weighted_batch(n_layers, mu_s, mu_a, g, n_layer, thickness, n_upper, n_lower, k_lower, mu0,
+                        photons, seed, streams=None, max_steps=1 << 40, n_threads=None):
+    """Weighted-packet (MCML) walk of many items, threaded.  Returns
+    (tallies float64 [I, 8], steps uint64 [I, 2] = photon-steps, capped)."""
+    n_layers = np.ascontiguousarray(n_layers, np.int32)
+    I = len(n_layers)
+    mu_s = _f64(mu_s).reshape(I, -1)
+    L = mu_s.shape[1]
+    arrs = [_f64(a).reshape(I, L) for a in (mu_s, mu_a, g, n_layer, thickness)]
+    items = [_f64(a).reshape(I) for a in (n_upper, n_lower, k_lower, mu0)]
+    photons = np.ascontiguousarray(photons, np.uint64)
+    st = None if streams is None else np.ascontiguousarray(streams, np.uint32)
+    out = np.zeros((I, N_WTALLY), np.float64)
+    steps = np.zeros((I, 2), np.uint64)
+    nt = n_threads or default_threads()
+    rc = _load().orc_walk_weighted_batch(
+        I, L, n_layers.ctypes.data_as(POINTER(c_int32)), *[_dp(a) for a in arrs],
+        *[_dp(a) for a in items], photons.ctypes.data_as(POINTER(c_uint64)),
+        None if st is None else st.ctypes.data_as(POINTER(c_uint32)), seed, max_steps, nt, _dp(out),
+        steps.ctypes.data_as(POINTER(c_uint64)))
+    if rc != 0:
+        raise ValueError("orc_walk_weighted_batch rejected its arguments")
+    return out, steps
 
 
 def mie_nmax(y_abs: float) -> int:

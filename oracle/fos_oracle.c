@@ -16,7 +16,8 @@
  *   - Henyey-Greenstein cosine sampling, textbook inversion (the sampler used
  *     by MCML, ref. [45]).
  *   - The analog photon walk through a multi-layer slab tracking only depth z
- *     and the direction cosine to the z axis (Methodology, Photon transport).
+ *     and the direction cosine to the z axis (Methodology, Photon transport),
+ *     and its weighted-packet form with Russian roulette (MCML, ref. [45]).
  *   - Lorenz-Mie coefficients of a sphere in an absorbing host, eqs. (1)-(5),
  *     evaluated with the Bohren-Huffman logarithmic-derivative recursion
  *     instead of the garbled closed forms (6)-(9); cross sections eqs.
@@ -322,6 +323,189 @@ int orc_walk_batch(int n_items, int max_layers, const int32_t* n_layers, const d
     pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
     for (int k = 0; k < n_threads; ++k) pthread_create(&th[k], NULL, batch_worker, &J);
     for (int k = 0; k < n_threads; ++k) pthread_join(th[k], NULL);
+    free(th);
+    free(us);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Weighted-packet walk (the MCML form of ref. [45])                          */
+/* ------------------------------------------------------------------------- */
+/* The same stacks, boundaries and counter layout as the analog walk, with the
+ * photon carried as a packet of weight W instead of being absorbed whole:
+ *   - launch: the specular part R0 is tallied deterministically (no draw) and
+ *     the packet enters with W = 1 - R0;
+ *   - boundaries: as in the analog walk (all-or-none Fresnel decision with
+ *     U1); an exiting packet tallies its whole weight;
+ *   - interaction: the fraction mu_a/mu_t of W is deposited (absorbed), the
+ *     rest scatters (HG with U2, azimuth U3) -- there is no albedo draw;
+ *   - roulette: when W falls below WT_THRESHOLD the packet survives with
+ *     probability WT_CHANCE (decided by U1) and weight W / WT_CHANCE, else it
+ *     ends; a packet whose weight became exactly zero ends at once.
+ * Tallies per item (double): specular R (sum of R0), diffuse R, A, T (sums of
+ * weight), the sums of squares of each photon's diffuse-R, A and T totals
+ * (variances), and the number of photons ended by roulette.  Every estimate
+ * is unbiased; R + A + T = 1 holds in expectation, not photon by photon. */
+#define WT_THRESHOLD 1e-4
+#define WT_CHANCE 0.1
+enum { WT_RSPEC = 0, WT_RDIFF, WT_ABS, WT_TRANS, WT_RDIFF2, WT_ABS2, WT_TRANS2, WT_ROULETTE, WT_N };
+
+static void walk_range_weighted(const orc_stack* S, uint64_t seed, uint64_t p_begin, uint64_t p_end,
+                                uint64_t max_steps, double wt[WT_N], uint64_t* steps, uint64_t* capped)
+{
+    double u[4];
+    const double R0 = orc_fresnel(S->mu0, S->n_up, S->n[0], 0.0);
+    for (uint64_t p = p_begin; p < p_end; ++p) {
+        wt[WT_RSPEC] += R0;
+        double w = 1.0 - R0, a = 0.0;
+        double r = S->n_up / S->n[0];
+        double uz = sqrt(1.0 - r * r * (1.0 - S->mu0 * S->mu0));
+        int l = 0;
+        double z = 0.0, s = 0.0;
+        uint64_t k = 0;
+        int out = -1;   /* WT_RDIFF or WT_TRANS when the packet leaves the stack */
+        if (w > 0.0) {
+            for (;;) {
+                ++k;
+                if (k > max_steps) { ++*capped; k = max_steps; break; }
+                draw_block(p, (uint32_t)k, S->stream, seed, u);
+                if (s == 0.0) s = -log(1.0 - u[0]);
+                double mut = S->mus[l] + S->mua[l];
+                if (uz == 0.0) {
+                    if (mut == 0.0) { ++*capped; break; }
+                    goto interact;
+                }
+                {
+                    double db = (uz > 0.0) ? (S->zbot[l] - z) / uz : (S->ztop[l] - z) / uz;
+                    if (mut * db <= s) {
+                        s -= mut * db;
+                        if (s < 0.0) s = 0.0;
+                        int down = uz > 0.0;
+                        z = down ? S->zbot[l] : S->ztop[l];
+                        int exit_ = down ? (l == S->L - 1) : (l == 0);
+                        double nt, kt = 0.0;
+                        if (down) {
+                            if (exit_) { nt = S->n_lo; kt = S->k_lo; }
+                            else nt = S->n[l + 1];
+                        } else {
+                            nt = exit_ ? S->n_up : S->n[l - 1];
+                        }
+                        double ci = fabs(uz);
+                        double R = orc_fresnel(ci, S->n[l], nt, kt);
+                        if (u[1] < R) {
+                            uz = -uz;
+                        } else if (exit_) {
+                            out = down ? WT_TRANS : WT_RDIFF;
+                            break;
+                        } else {
+                            double rr = S->n[l] / nt;
+                            double ct = sqrt(1.0 - rr * rr * (1.0 - ci * ci));
+                            uz = down ? ct : -ct;
+                            l += down ? 1 : -1;
+                        }
+                        continue;
+                    }
+                    z += uz * s / mut;
+                    s = 0.0;
+                }
+            interact:
+                {
+                    double dw = w * (S->mua[l] / mut);   /* exactly w without scattering */
+                    a += dw;
+                    w -= dw;
+                    if (w <= 0.0) { w = 0.0; break; }
+                    double ct = orc_hg_cos(S->g[l], u[2]);
+                    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+                    double so = sqrt(fmax(0.0, 1.0 - uz * uz));
+                    uz = uz * ct + so * st * cos(2.0 * M_PI * u[3]);
+                    if (uz > 1.0) uz = 1.0;
+                    if (uz < -1.0) uz = -1.0;
+                    if (w < WT_THRESHOLD) {
+                        if (u[1] < WT_CHANCE) w /= WT_CHANCE;
+                        else { w = 0.0; wt[WT_ROULETTE] += 1.0; break; }
+                    }
+                }
+            }
+        }
+        if (out >= 0) {
+            wt[out] += w;
+            wt[out == WT_TRANS ? WT_TRANS2 : WT_RDIFF2] += w * w;
+        }
+        wt[WT_ABS] += a;
+        wt[WT_ABS2] += a * a;
+        *steps += k;
+    }
+}
+
+typedef struct {
+    batch_job B;
+    double* wtallies;             /* [n_items * WT_N] */
+    uint64_t* wsteps;             /* [n_items * 2]: photon-steps, capped photons */
+    pthread_mutex_t lock;
+} wbatch_job;
+
+static void* wbatch_worker(void* arg)
+{
+    wbatch_job* WJ = (wbatch_job*)arg;
+    batch_job* J = &WJ->B;
+    for (;;) {
+        uint64_t u = __atomic_fetch_add(&J->next, 1, __ATOMIC_RELAXED);
+        if (u >= J->n_units) break;
+        int lo = 0, hi = J->n_items;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) / 2;
+            if (J->unit_start[mid] <= u) lo = mid; else hi = mid;
+        }
+        int i = lo;
+        uint64_t c = u - J->unit_start[i];
+        uint64_t p0 = c * J->chunk;
+        uint64_t p1 = p0 + J->chunk;
+        if (p1 > J->photons[i]) p1 = J->photons[i];
+        size_t o = (size_t)i * J->max_layers;
+        orc_stack S;
+        build_stack(&S, J->n_layers[i], J->mus + o, J->mua + o, J->g + o, J->n + o, J->t + o,
+                    J->n_up[i], J->n_lo[i], J->k_lo[i], J->mu0[i],
+                    J->streams ? J->streams[i] : (uint32_t)i);
+        double wt[WT_N] = {0};
+        uint64_t st = 0, cap = 0;
+        walk_range_weighted(&S, J->seed, p0, p1, J->max_steps, wt, &st, &cap);
+        pthread_mutex_lock(&WJ->lock);
+        for (int k = 0; k < WT_N; ++k) WJ->wtallies[(size_t)i * WT_N + k] += wt[k];
+        WJ->wsteps[2 * (size_t)i] += st;
+        WJ->wsteps[2 * (size_t)i + 1] += cap;
+        pthread_mutex_unlock(&WJ->lock);
+    }
+    return NULL;
+}
+
+/* Weighted-packet walk of a batch (arrays as orc_walk_batch).  tallies
+ * [n_items * 8] (doubles, see WT_*) and steps [n_items * 2] (photon-steps,
+ * capped photons) are overwritten.  Sums over photon chunks are added in an
+ * order that depends on thread timing, so results agree to rounding. */
+int orc_walk_weighted_batch(int n_items, int max_layers, const int32_t* n_layers, const double* mus,
+                            const double* mua, const double* g, const double* n, const double* t,
+                            const double* n_up, const double* n_lo, const double* k_lo, const double* mu0,
+                            const uint64_t* photons, const uint32_t* streams, uint64_t seed,
+                            uint64_t max_steps, int n_threads, double* tallies, uint64_t* steps)
+{
+    if (n_items < 0 || max_layers < 1 || max_layers > ORC_MAX_LAYERS || n_threads < 1) return -1;
+    memset(tallies, 0, sizeof(double) * (size_t)n_items * WT_N);
+    memset(steps, 0, sizeof(uint64_t) * (size_t)n_items * 2);
+    const uint64_t chunk = 8192;
+    uint64_t* us = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)n_items + 1));
+    us[0] = 0;
+    for (int i = 0; i < n_items; ++i) us[i + 1] = us[i] + (photons[i] + chunk - 1) / chunk;
+    wbatch_job WJ;
+    batch_job B = {n_items, max_layers, n_layers, mus, mua, g, n, t, n_up, n_lo, k_lo, mu0,
+                   photons, streams, seed, max_steps, chunk, us, us[n_items], 0, NULL};
+    WJ.B = B;
+    WJ.wtallies = tallies;
+    WJ.wsteps = steps;
+    pthread_mutex_init(&WJ.lock, NULL);
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    for (int k = 0; k < n_threads; ++k) pthread_create(&th[k], NULL, wbatch_worker, &WJ);
+    for (int k = 0; k < n_threads; ++k) pthread_join(th[k], NULL);
+    pthread_mutex_destroy(&WJ.lock);
     free(th);
     free(us);
     return 0;

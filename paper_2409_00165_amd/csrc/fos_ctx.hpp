@@ -55,6 +55,7 @@ struct fos_ctx {
     // prepared problem
     int32_t n_items = 0, max_layers = 0;
     bool prepared = false;
+    uint64_t max_photons = 0;                // largest photon budget of the prepared problem
     float4* table = nullptr;
     size_t table_bytes = 0;
     unsigned long long* chunk_prefix = nullptr;    // [n_items + 1]

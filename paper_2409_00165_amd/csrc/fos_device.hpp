@@ -33,6 +33,15 @@ enum LayerFlags : uint32_t {
 };
 
 enum Outcome : int { kRSpec = 0, kRDiff = 1, kAbs = 2, kTrans = 3, kCap = 4, kSteps = 5, kNTally = 6 };
+// weighted-packet tallies: weights in units of 2^-36 (exact integer sums, so
+// results do not depend on the order photons finish in), photon counts, steps
+enum WOutcome : int {
+    kWRSpec = 0, kWRDiff = 1, kWAbs = 2, kWTrans = 3, kWRDiff2 = 4, kWAbs2 = 5, kWTrans2 = 6,
+    kWRoulette = 7, kWCap = 8, kWSteps = 9, kWPhotons = 10, kNTallyW = 11
+};
+constexpr double kWeightUnit = 68719476736.0;   // 2^36
+constexpr float kRouletteThreshold = 1e-4f;       // packets below this weight play roulette
+constexpr float kRouletteChance = 0.1f;           // and survive with this probability
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products

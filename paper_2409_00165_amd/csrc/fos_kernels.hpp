@@ -29,6 +29,7 @@ struct PackArgs {
     const uint64_t* photons;
     float4* table;
     unsigned long long* err;
+    unsigned long long* max_photons;   // largest photon budget of the batch
 };
 
 struct WalkArgs {
@@ -99,13 +100,15 @@ hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st);
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
-hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, hipStream_t st);
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, int nt,
+                        hipStream_t st);
 hipError_t launch_chunk_scan(const float4* table, int rec_f4, int n_items, int chunk, uint64_t photon_cap,
                              unsigned long long* prefix, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
-hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st);
+hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted = false);
 hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st);
-size_t walk_lds_bytes(int block_size, int max_layers);
+hipError_t launch_weighted_fractions(int n, const unsigned long long* tallies, float* rat, float* se, hipStream_t st);
+size_t walk_lds_bytes(int block_size, int max_layers, bool weighted = false);
 hipError_t launch_philox_words(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
                                uint64_t seed, uint32_t* out, hipStream_t st);
 hipError_t launch_eval_fresnel(int n, const float* c, const float* ni, const float* nt, const float* kt,

@@ -46,7 +46,11 @@ constexpr size_t kPkOffL1 = 0;
 constexpr size_t kPkOffL2 = kPkOffL1 + (size_t)16 * 64 * 8;
 constexpr size_t kPkOffOut = kPkOffL2 + 3 * kPkHid;
 constexpr size_t kPkParams = kPkOffOut + (size_t)8 * 64 * 8;
-constexpr int kInferTile = 128;                        // rows per inference workgroup
+#ifndef FOS_INFER_TILE
+#define FOS_INFER_TILE 128
+#endif
+constexpr int kInferTile = FOS_INFER_TILE;             // rows per inference workgroup (64 or 128)
+static_assert(kInferTile == 64 || kInferTile == 128, "inference tile must be 64 or 128 rows");
 
 struct InferArgs {
     int64_t n;

@@ -82,6 +82,7 @@ __global__ void pack_items(PackArgs a)
     const double uz0 = s2t < 1.0 ? sqrt(1.0 - s2t) : 0.0;
     rec[0] = make_float4((float)R0, (float)uz0, nl, kl);
     const uint64_t N = a.photons[i];
+    atomicMax(a.max_photons, (unsigned long long)N);
     rec[1] = make_float4(__uint_as_float((uint32_t)N), __uint_as_float((uint32_t)(N >> 32)),
                          __int_as_float(L), __int_as_float(i));
     for (int l = 0; l < L; ++l) {
@@ -109,11 +110,11 @@ __global__ void pack_items(PackArgs a)
     }
 }
 
-__global__ void reset_run(unsigned long long* tallies, unsigned long long* counter, int n_items)
+__global__ void reset_run(unsigned long long* tallies, unsigned long long* counter, int n_items, int nt)
 {
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t j = tid; j < (size_t)n_items * kNTally; j += stride) tallies[j] = 0ull;
+    for (size_t j = tid; j < (size_t)n_items * nt; j += stride) tallies[j] = 0ull;
     if (tid == 0) *counter = 0ull;
 }
 
@@ -199,9 +200,19 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int kStepsPerCheck>
+__device__ __forceinline__ unsigned long long weight_units(double w)
+{
+    return (unsigned long long)__double2ull_rn(w * kWeightUnit);
+}
+
+// WEIGHTED selects the weighted-packet (MCML) form: no specular or albedo
+// draws; the packet deposits mu_a/mu_t of its weight at each interaction,
+// always scatters, plays roulette below kRouletteThreshold, and tallies
+// weights (kNTallyW counters) instead of photon counts (kNTally).
+template <int kStepsPerCheck, bool WEIGHTED>
 __global__ void walk(WalkArgs a)
 {
+    constexpr int NT = WEIGHTED ? kNTallyW : kNTally;
     extern __shared__ float4 smem[];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -209,12 +220,12 @@ __global__ void walk(WalkArgs a)
     const int rf = a.rec_f4;
     float4* tab = smem + (size_t)wv * kSlots * rf;                         // [kSlots][rf]
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(smem + (size_t)nwaves * kSlots * rf) +
-                              (size_t)wv * kSlots * kNTally;                 // [kSlots][6]
+                              (size_t)wv * kSlots * NT;                      // [kSlots][NT]
     int* slot_item = reinterpret_cast<int*>(reinterpret_cast<unsigned long long*>(
-                         smem + (size_t)nwaves * kSlots * rf) + (size_t)nwaves * kSlots * kNTally) +
+                         smem + (size_t)nwaves * kSlots * rf) + (size_t)nwaves * kSlots * NT) +
                      wv * kSlots;                                            // [kSlots]
 
-    for (int j = lane; j < kSlots * kNTally; j += 64) cnt[j] = 0ull;
+    for (int j = lane; j < kSlots * NT; j += 64) cnt[j] = 0ull;
     if (lane < kSlots) slot_item[lane] = -1;
     wave_sync_lds();
 
@@ -227,6 +238,7 @@ __global__ void walk(WalkArgs a)
     int slot = 0, layer = 0;
     uint32_t item = 0, p_lo = 0, p_hi = 0, k = 0;
     float z = 0.f, uz = 1.f, s = 0.f;
+    float wgt = 0.f, absd = 0.f;   // weighted form: packet weight, weight deposited so far
     LaneLayer P;
     P.mut = P.alb = P.inv_mut = P.thick = P.hG = P.hh = P.q1 = P.q2 = P.m_up = P.m_dn = P.n = 0.f;
     P.flags = 0u;
@@ -273,12 +285,12 @@ __global__ void walk(WalkArgs a)
                 if (c_item != src_item) {
                     // recycle slot ns: flush its counts, stage the new item
                     const int old = slot_item[ns];
-                    if (old >= 0 && lane < kNTally) {
-                        const unsigned long long v = cnt[ns * kNTally + lane];
-                        if (v) atomicAdd(a.tallies + (size_t)old * kNTally + lane, v);
+                    if (old >= 0 && lane < NT) {
+                        const unsigned long long v = cnt[ns * NT + lane];
+                        if (v) atomicAdd(a.tallies + (size_t)old * NT + lane, v);
                     }
                     wave_sync_lds();
-                    if (lane < kNTally) cnt[ns * kNTally + lane] = 0ull;
+                    if (lane < NT) cnt[ns * NT + lane] = 0ull;
                     for (int j = lane; j < rf; j += 64) tab[ns * rf + j] = a.table[(size_t)c_item * rf + j];
                     if (lane == 0) slot_item[ns] = c_item;
                     wave_sync_lds();
@@ -301,10 +313,18 @@ __global__ void walk(WalkArgs a)
                 const float4 h0 = sr[0];
                 p_lo = (uint32_t)p; p_hi = (uint32_t)(p >> 32);
                 item = (uint32_t)src_item;
-                const uint4 x = philox4x32_10(p_lo, p_hi, 0u, item, k0, k1);
-                if (u24(x.y) < h0.x) {
-                    spec = true;                        // specular reflection
+                bool enter;
+                if constexpr (WEIGHTED) {
+                    // the specular part leaves as weight, no draw
+                    wgt = 1.0f - h0.x;
+                    absd = 0.f;
+                    enter = wgt > 0.f;
                 } else {
+                    const uint4 x = philox4x32_10(p_lo, p_hi, 0u, item, k0, k1);
+                    enter = !(u24(x.y) < h0.x);
+                    spec = !enter;                      // specular reflection
+                }
+                if (enter) {
                     alive = true;
                     slot = src_slot;
                     layer = 0;
@@ -312,9 +332,17 @@ __global__ void walk(WalkArgs a)
                     load_layer(sr, 0, P);
                 }
             }
-            const uint64_t sm = ballot64(spec);
-            if (sm != 0ull && lane == 0)
-                atomicAdd(cnt + src_slot * kNTally + kRSpec, (unsigned long long)__popcll(sm));
+            if constexpr (WEIGHTED) {
+                if (take > 0 && lane == 0) {
+                    atomicAdd(cnt + src_slot * NT + kWRSpec,
+                              (unsigned long long)take * weight_units((double)tab[src_slot * rf].x));
+                    atomicAdd(cnt + src_slot * NT + kWPhotons, (unsigned long long)take);
+                }
+            } else {
+                const uint64_t sm = ballot64(spec);
+                if (sm != 0ull && lane == 0)
+                    atomicAdd(cnt + src_slot * NT + kRSpec, (unsigned long long)__popcll(sm));
+            }
             src_next += (uint64_t)take;
             dead = ballot64(!alive);
         }
@@ -378,14 +406,30 @@ __global__ void walk(WalkArgs a)
                         }
                     }
                     if (interact) {
-                        if (U1 < P.alb) {
+                        bool scatter;
+                        if constexpr (WEIGHTED) {
+                            // deposit mu_a/mu_t of the weight, scatter the rest
+                            const float wn = wgt * P.alb;
+                            absd += wgt - wn;
+                            wgt = wn;
+                            scatter = wgt > 0.f;
+                            if (!scatter) term = kAbs;
+                        } else {
+                            scatter = U1 < P.alb;
+                            if (!scatter) term = kAbs;
+                        }
+                        if (scatter) {
                             const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,
                                                    u24(x.z));
                             const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
                             const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
                             uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);
-                        } else {
-                            term = kAbs;
+                            if constexpr (WEIGHTED) {
+                                if (wgt < kRouletteThreshold) {
+                                    if (U1 < kRouletteChance) wgt = wgt / kRouletteChance;
+                                    else term = kWRoulette;
+                                }
+                            }
                         }
                     }
                 }
@@ -393,22 +437,45 @@ __global__ void walk(WalkArgs a)
             // ---- tallies of photons that finished in this step ----
             const uint64_t tm = ballot64(term >= 0);
             if (tm != 0ull) {
-                if (term >= 0) {
-                    alive = false;
-                    atomicAdd(cnt + slot * kNTally + kSteps, (unsigned long long)k);
-                }
-                const int lead = __builtin_ctzll(tm);
-                const int s0 = __shfl(slot, lead);
-                if (ballot64(term >= 0 && slot != s0) == 0ull) {
-                    // every finishing lane shares slot s0: one popcount per outcome
-                    unsigned long long* c0 = cnt + s0 * kNTally;
-#pragma unroll
-                    for (int o = kRDiff; o <= kCap; ++o) {
-                        const uint64_t bo = ballot64(term == o);
-                        if (bo != 0ull && lane == 0) atomicAdd(c0 + o, (unsigned long long)__popcll(bo));
+                if constexpr (WEIGHTED) {
+                    // per-lane: the packet's deposits, its exit weight, the counts
+                    if (term >= 0) {
+                        alive = false;
+                        unsigned long long* c0 = cnt + slot * NT;
+                        atomicAdd(c0 + kWSteps, (unsigned long long)k);
+                        const double ad = (double)absd;
+                        if (ad > 0.0) {
+                            atomicAdd(c0 + kWAbs, weight_units(ad));
+                            atomicAdd(c0 + kWAbs2, weight_units(ad * ad));
+                        }
+                        if (term == kTrans || term == kRDiff) {
+                            const double w = (double)wgt;
+                            atomicAdd(c0 + (term == kTrans ? kWTrans : kWRDiff), weight_units(w));
+                            atomicAdd(c0 + (term == kTrans ? kWTrans2 : kWRDiff2), weight_units(w * w));
+                        } else if (term == kWRoulette) {
+                            atomicAdd(c0 + kWRoulette, 1ull);
+                        } else if (term == kCap) {
+                            atomicAdd(c0 + kWCap, 1ull);
+                        }
                     }
-                } else if (term >= 0) {
-                    atomicAdd(cnt + slot * kNTally + term, 1ull);
+                } else {
+                    if (term >= 0) {
+                        alive = false;
+                        atomicAdd(cnt + slot * NT + kSteps, (unsigned long long)k);
+                    }
+                    const int lead = __builtin_ctzll(tm);
+                    const int s0 = __shfl(slot, lead);
+                    if (ballot64(term >= 0 && slot != s0) == 0ull) {
+                        // every finishing lane shares slot s0: one popcount per outcome
+                        unsigned long long* c0 = cnt + s0 * NT;
+#pragma unroll
+                        for (int o = kRDiff; o <= kCap; ++o) {
+                            const uint64_t bo = ballot64(term == o);
+                            if (bo != 0ull && lane == 0) atomicAdd(c0 + o, (unsigned long long)__popcll(bo));
+                        }
+                    } else if (term >= 0) {
+                        atomicAdd(cnt + slot * NT + term, 1ull);
+                    }
                 }
                 if (__popcll(ballot64(!alive)) >= a.refill_min) break;
             }
@@ -419,24 +486,28 @@ __global__ void walk(WalkArgs a)
     wave_sync_lds();
     for (int sl = 0; sl < kSlots; ++sl) {
         const int it = slot_item[sl];
-        if (it >= 0 && lane < kNTally) {
-            const unsigned long long v = cnt[sl * kNTally + lane];
-            if (v) atomicAdd(a.tallies + (size_t)it * kNTally + lane, v);
+        if (it >= 0 && lane < NT) {
+            const unsigned long long v = cnt[sl * NT + lane];
+            if (v) atomicAdd(a.tallies + (size_t)it * NT + lane, v);
         }
     }
 }
 
-size_t walk_lds_bytes(int block_size, int max_layers)
+size_t walk_lds_bytes(int block_size, int max_layers, bool weighted)
 {
     const int nw = block_size / 64;
+    const int nt = weighted ? kNTallyW : kNTally;
     return (size_t)nw * kSlots * rec_f4(max_layers) * sizeof(float4) +
-           (size_t)nw * kSlots * kNTally * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int);
+           (size_t)nw * kSlots * nt * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int);
 }
 
-hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st)
+hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted)
 {
-    const size_t lds = walk_lds_bytes(block, a.max_layers);
-    hipLaunchKernelGGL(walk<4>, dim3(grid), dim3(block), lds, st, a);
+    const size_t lds = walk_lds_bytes(block, a.max_layers, weighted);
+    if (weighted)
+        hipLaunchKernelGGL((walk<4, true>), dim3(grid), dim3(block), lds, st, a);
+    else
+        hipLaunchKernelGGL((walk<4, false>), dim3(grid), dim3(block), lds, st, a);
     return hipGetLastError();
 }
 
@@ -448,12 +519,13 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, hipStream_t st)
+hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, int nt,
+                        hipStream_t st)
 {
-    int blocks = (int)(((size_t)n_items * kNTally + 255) / 256);
+    int blocks = (int)(((size_t)n_items * nt + 255) / 256);
     if (blocks < 1) blocks = 1;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(reset_run, dim3(blocks), dim3(256), 0, st, tallies, counter, n_items);
+    hipLaunchKernelGGL(reset_run, dim3(blocks), dim3(256), 0, st, tallies, counter, n_items, nt);
     return hipGetLastError();
 }
 
@@ -491,6 +563,41 @@ __global__ void fractions_k(int n, const unsigned long long* t, float* rat)
     rat[3 * (size_t)i + 0] = (float)((double)(ti[0] + ti[1]) / N);
     rat[3 * (size_t)i + 1] = (float)((double)ti[2] / N);
     rat[3 * (size_t)i + 2] = (float)((double)ti[3] / N);
+}
+
+// weighted tallies -> (R, A, T) means and the standard errors of their
+// estimates (the specular part is exact, so R's error is the diffuse part's)
+__global__ void weighted_fractions_k(int n, const unsigned long long* t, float* rat, float* se)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long* ti = t + (size_t)i * kNTallyW;
+    const double N = (double)ti[kWPhotons];
+    float* r = rat + 3 * (size_t)i;
+    float* e = se ? se + 3 * (size_t)i : nullptr;
+    if (N == 0.0) {
+        r[0] = r[1] = r[2] = 0.0f;
+        if (e) e[0] = e[1] = e[2] = 0.0f;
+        return;
+    }
+    const double u = 1.0 / kWeightUnit;
+    const double mean_rd = (double)ti[kWRDiff] * u / N, mean_a = (double)ti[kWAbs] * u / N;
+    const double mean_t = (double)ti[kWTrans] * u / N;
+    r[0] = (float)((double)ti[kWRSpec] * u / N + mean_rd);
+    r[1] = (float)mean_a;
+    r[2] = (float)mean_t;
+    if (e) {
+        const double m2[3] = {(double)ti[kWRDiff2] * u / N, (double)ti[kWAbs2] * u / N, (double)ti[kWTrans2] * u / N};
+        const double m1[3] = {mean_rd, mean_a, mean_t};
+        for (int c = 0; c < 3; ++c) e[c] = (float)sqrt(fmax(m2[c] - m1[c] * m1[c], 0.0) / N);
+    }
+}
+
+hipError_t launch_weighted_fractions(int n, const unsigned long long* tallies, float* rat, float* se, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(weighted_fractions_k, dim3((n + 255) / 256), dim3(256), 0, st, n, tallies, rat, se);
+    return hipGetLastError();
 }
 
 hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st)

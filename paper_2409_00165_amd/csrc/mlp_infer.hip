@@ -19,11 +19,11 @@
 // from LDS.  A lane's accumulator then holds 4 consecutive neurons of one
 // row, so the bias + GELU epilogue writes 8-byte bf16 quads back to LDS.
 //
-// Work split inside a workgroup (4 waves, 128 rows): wave w owns neurons
-// 64w .. 64w+63 of every hidden layer for all 128 rows (32 accumulator tiles)
-// and rows 32w .. 32w+31 of the output layer; the lanes that end with a row's
-// logits keep that row's ensemble sum / min / max in registers across the
-// members.
+// Work split inside a workgroup (4 waves, TILE = kInferTile rows): wave w
+// owns neurons 64w .. 64w+63 of every hidden layer for all rows (TILE/4
+// accumulator tiles) and TILE/64 row tiles of the output layer; the lanes that
+// end with a row's logits keep that row's ensemble sum / min / max in
+// registers across the members.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -38,7 +38,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = kInferTile;            // rows per workgroup
 constexpr int kHRow = kHidden + 8;           // bf16 per LDS activation row (528 B: conflict-free b128 reads)
 constexpr int kXRow = 32 + 8;                // bf16 per LDS input-fragment row
 
@@ -59,8 +58,9 @@ __device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// bias + GELU of a wave's 64 neurons x 128 rows, written to H as bf16 quads
-__device__ __forceinline__ void epilogue(floatx4 (&acc)[4][kTile / 16], const float* __restrict__ bias, __bf16* H,
+// bias + GELU of a wave's 64 neurons x TILE rows, written to H as bf16 quads
+template <int TILE>
+__device__ __forceinline__ void epilogue(floatx4 (&acc)[4][TILE / 16], const float* __restrict__ bias, __bf16* H,
                                          int w, int q, int c16)
 {
 #pragma unroll
@@ -68,7 +68,7 @@ __device__ __forceinline__ void epilogue(floatx4 (&acc)[4][kTile / 16], const fl
         const int n0 = 16 * (4 * w + j) + 4 * q;
         const float b0 = bias[n0], b1 = bias[n0 + 1], b2 = bias[n0 + 2], b3 = bias[n0 + 3];
 #pragma unroll
-        for (int i = 0; i < kTile / 16; ++i) {
+        for (int i = 0; i < TILE / 16; ++i) {
             bf16x4 v;
             v[0] = (__bf16)gelu_sig(acc[j][i][0] + b0);
             v[1] = (__bf16)gelu_sig(acc[j][i][1] + b1);
@@ -117,8 +117,11 @@ __global__ void pack_infer_kernel(const float* __restrict__ params, __bf16* __re
     pk[(size_t)m * kPkParams + e] = (__bf16)v;
 }
 
-__global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
+template <int TILE>
+__global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(InferArgs a)
 {
+    constexpr int kTile = TILE;                    // rows per workgroup
+    constexpr int OT = TILE / 64;                  // output-layer row tiles per wave
     __shared__ __attribute__((aligned(16))) __bf16 H[kTile * kHRow];
     __shared__ __attribute__((aligned(16))) __bf16 X[kTile * kXRow];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
@@ -146,9 +149,9 @@ __global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
         *reinterpret_cast<bf16x8*>(xr + 24) = z8;
     }
 
-    float sum[2][3], mn[2][3], mx[2][3];
+    float sum[OT][3], mn[OT][3], mx[OT][3];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < OT; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) { sum[i][c] = 0.0f; mn[i][c] = 1e30f; mx[i][c] = -1e30f; }
 
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
                 for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wf[j], xf, zero4);
             }
         }
-        epilogue(acc, F + kOffB1, H, w, q, c16);
+        epilogue<TILE>(acc, F + kOffB1, H, w, q, c16);
 
         // hidden layers 2..4, in place in H.  The weight fragments of k-step
         // s + 1 are in flight while k-step s multiplies (two register sets
@@ -220,25 +223,27 @@ __global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
             }
             step(wb, 7);
             __syncthreads();   // every wave done reading this layer's input
-            epilogue(acc, F + boff, H, w, q, c16);
+            epilogue<TILE>(acc, F + boff, H, w, q, c16);
         }
 
-        // output layer: wave w takes rows 32w .. 32w+31 (two tiles)
+        // output layer: wave w takes the OT row tiles OT w .. OT w + OT - 1
         __syncthreads();
-        floatx4 o[2] = {zero4, zero4};
+        floatx4 o[OT];
+#pragma unroll
+        for (int i = 0; i < OT; ++i) o[i] = zero4;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const bf16x8 wf = *reinterpret_cast<const bf16x8*>(P + kPkOffOut + ((size_t)s * 64 + lane) * 8);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < OT; ++i) {
                 const bf16x8 hf =
-                    *reinterpret_cast<const bf16x8*>(H + (16 * (2 * w + i) + c16) * kHRow + 32 * s + 8 * q);
+                    *reinterpret_cast<const bf16x8*>(H + (16 * (OT * w + i) + c16) * kHRow + 32 * s + 8 * q);
                 o[i] = mfma(wf, hf, o[i]);
             }
         }
-        if (q == 0) {   // lanes 0..15 hold logits 0..3 of rows 32w + 16i + lane
+        if (q == 0) {   // lanes 0..15 hold logits 0..3 of rows 16 (OT w + i) + lane
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < OT; ++i) {
                 float l[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) l[c] = o[i][c] + F[kOffB5 + c];
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { e[c] = __expf(l[c] - lm); se += e[c]; }
                 const float is = 1.0f / se;
-                const int64_t row = row0 + 32 * w + 16 * i + c16;
+                const int64_t row = row0 + 16 * (OT * w + i) + c16;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     // the rounded probability is what the members output holds;
@@ -266,8 +271,8 @@ __global__ __launch_bounds__(256, 2) void mlp_infer_kernel(InferArgs a)
 
     if (q == 0) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int64_t row = row0 + 32 * w + 16 * i + c16;
+        for (int i = 0; i < OT; ++i) {
+            const int64_t row = row0 + 16 * (OT * w + i) + c16;
             if (row >= a.n) continue;
             float spread = 0.0f;
 #pragma unroll
@@ -296,9 +301,9 @@ hipError_t launch_pack_infer(const float* params, __bf16* pk, int nets, hipStrea
 hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    const int64_t blocks = (a.n + kTile - 1) / kTile;
+    const int64_t blocks = (a.n + kInferTile - 1) / kInferTile;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(mlp_infer_kernel<kInferTile>, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -189,13 +189,17 @@ fos_status fos_mc_prepare(fos_ctx* c, const fos_mc_problem* p, void* hip_stream)
     e = grow(c->chunk_prefix, c->chunk_prefix_bytes, ((size_t)p->n_items + 1) * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail(c, e, "work queue");
     if (p->n_items > 0) {
-        if ((e = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess) return hip_fail(c, e, "reset");
+        if ((e = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess ||
+            (e = fos::launch_fill_u64(c->err_dev + 1, 0ull, 1, st)) != hipSuccess)
+            return hip_fail(c, e, "reset");
         fos::PackArgs a{p->n_items, p->max_layers, p->n_layers, p->mu_s, p->mu_a, p->g, p->n_layer,
                         p->thickness, p->n_upper, p->n_lower, p->k_lower, p->mu0, p->photons, c->table,
-                        c->err_dev};
+                        c->err_dev, c->err_dev + 1};
         if ((e = fos::launch_pack(a, st)) != hipSuccess) return hip_fail(c, e, "pack kernel");
         if ((e = hipMemcpyAsync(c->err_host, c->err_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
-            hipSuccess)
+                hipSuccess ||
+            (e = hipMemcpyAsync(&c->aux_host[3], c->err_dev + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                st)) != hipSuccess)
             return hip_fail(c, e, "verdict copy");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "prepare");
         const unsigned long long w = *c->err_host;
@@ -208,6 +212,7 @@ fos_status fos_mc_prepare(fos_ctx* c, const fos_mc_problem* p, void* hip_stream)
     }
     c->n_items = p->n_items;
     c->max_layers = p->max_layers;
+    c->max_photons = p->n_items > 0 ? (uint64_t)c->aux_host[3] : 0;
     c->prepared = true;
     c->prepare_epoch++;
     return FOS_OK;
@@ -215,9 +220,10 @@ fos_status fos_mc_prepare(fos_ctx* c, const fos_mc_problem* p, void* hip_stream)
 
 // Zero the tallies and the chunk counter, then rebuild the chunk prefix for
 // this launch's chunk size and photon cap (kernels only: graph-capturable).
-static hipError_t enqueue_queue_reset(fos_ctx* c, unsigned long long* tal, int chunk, uint64_t cap, hipStream_t st)
+static hipError_t enqueue_queue_reset(fos_ctx* c, unsigned long long* tal, int chunk, uint64_t cap, hipStream_t st,
+                                      int n_tally = fos::kNTally)
 {
-    hipError_t e = fos::launch_reset(tal, c->chunk_counter, c->n_items, st);
+    hipError_t e = fos::launch_reset(tal, c->chunk_counter, c->n_items, n_tally, st);
     if (e != hipSuccess) return e;
     return fos::launch_chunk_scan(c->table, fos::rec_f4(c->max_layers), c->n_items, chunk, cap, c->chunk_prefix, st);
 }
@@ -241,7 +247,7 @@ static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed
     return a;
 }
 
-fos_status fos_mc_execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies,
+static fos_status execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies, bool weighted,
                           void* hip_stream)
 {
     if (!c) return FOS_E_INVALID_ARG;
@@ -252,15 +258,59 @@ fos_status fos_mc_execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch
     const fos_mc_launch L = merge(c->defaults, launch);
     fos_status s = check_launch(c, L);
     if (s != FOS_OK) return s;
+    if (weighted && c->max_photons > (1ull << 27))
+        return fail(c, FOS_E_UNSUPPORTED, "weighted walk: at most 2^27 photons per item (2^-36 weight units)");
     DeviceGuard g(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
-    hipError_t e = enqueue_queue_reset(c, tal, L.chunk, 0, st);
+    hipError_t e = enqueue_queue_reset(c, tal, L.chunk, 0, st, weighted ? fos::kNTallyW : fos::kNTally);
     if (e != hipSuccess) return hip_fail(c, e, "reset kernels");
     const fos::WalkArgs a = walk_args(c, L, seed, tal);
     const int grid = c->n_cu * L.blocks_per_cu;
-    if ((e = fos::launch_walk(a, grid, L.block_size, st)) != hipSuccess) return hip_fail(c, e, "walk kernel");
+    if ((e = fos::launch_walk(a, grid, L.block_size, st, weighted)) != hipSuccess)
+        return hip_fail(c, e, "walk kernel");
     return FOS_OK;
+}
+
+fos_status fos_mc_execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies,
+                          void* hip_stream)
+{
+    return execute(c, seed, launch, tallies, false, hip_stream);
+}
+
+fos_status fos_mc_execute_weighted(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch, uint64_t* tallies,
+                                   void* hip_stream)
+{
+    return execute(c, seed, launch, tallies, true, hip_stream);
+}
+
+fos_status fos_mc_run_weighted(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const fos_mc_launch* launch,
+                               uint64_t* tallies, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    if (launch) {
+        const fos_mc_launch L = merge(c->defaults, launch);
+        fos_status s = check_launch(c, L);
+        if (s != FOS_OK) return s;
+    }
+    if (p && p->n_items > 0 && !tallies) return fail(c, FOS_E_INVALID_ARG, "tallies is NULL");
+    fos_status s = fos_mc_prepare(c, p, hip_stream);
+    if (s != FOS_OK) return s;
+    return execute(c, seed, launch, tallies, true, hip_stream);
+}
+
+fos_status fos_mc_weighted_fractions(fos_ctx* c, int32_t n, const uint64_t* tallies, float* rat, float* se,
+                                     void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (n < 0) return fail(c, FOS_E_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return FOS_OK;
+    if (!tallies || !rat) return fail(c, FOS_E_INVALID_ARG, "tallies and rat must be non-NULL");
+    DeviceGuard g(c->device);
+    hipError_t e = fos::launch_weighted_fractions(n, reinterpret_cast<const unsigned long long*>(tallies), rat, se,
+                                                  reinterpret_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? FOS_OK : hip_fail(c, e, "weighted fractions kernel");
 }
 
 fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_mc_launch* best,

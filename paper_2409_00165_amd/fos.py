@@ -18,6 +18,10 @@ LIB_PATH = os.path.join(_PKG, "libfos_mc.so")
 FOS_MAX_LAYERS = 8
 N_TALLY = 6
 TALLY_NAMES = ("r_spec", "r_diff", "absorbed", "transmitted", "capped", "steps")
+N_TALLY_W = 11
+TALLY_W_NAMES = ("r_spec", "r_diff", "absorbed", "transmitted", "r_diff2", "absorbed2", "transmitted2",
+                 "roulette", "capped", "steps", "photons")
+WEIGHT_UNIT = float(1 << 36)
 STATUS = {0: "FOS_OK", 1: "FOS_E_INVALID_ARG", 2: "FOS_E_UNSUPPORTED", 3: "FOS_E_DEVICE",
           4: "FOS_E_OUT_OF_MEMORY", 5: "FOS_E_INTERNAL", 6: "FOS_E_NOT_PREPARED"}
 
@@ -118,6 +122,13 @@ def lib():
         L.fos_sur_load.restype = c_int
         L.fos_mc_fractions.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
         L.fos_mc_fractions.restype = c_int
+        L.fos_mc_execute_weighted.argtypes = [c_void_p, c_uint64, POINTER(fos_mc_launch), c_void_p, c_void_p]
+        L.fos_mc_execute_weighted.restype = c_int
+        L.fos_mc_run_weighted.argtypes = [c_void_p, POINTER(fos_mc_problem), c_uint64, POINTER(fos_mc_launch),
+                                          c_void_p, c_void_p]
+        L.fos_mc_run_weighted.restype = c_int
+        L.fos_mc_weighted_fractions.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fos_mc_weighted_fractions.restype = c_int
         L.fos_sweep_run.argtypes = [c_void_p, POINTER(fos_mc_problem), c_float, c_uint64, c_uint64, c_void_p,
                                     c_void_p, c_void_p, POINTER(ctypes.c_int64), c_void_p]
         L.fos_sweep_run.restype = c_int
@@ -293,6 +304,26 @@ def fos_mc_fractions(ctx, tallies, rat, stream=None) -> None:
     import torch
     n = tallies.numel() // N_TALLY
     _check(ctx, lib().fos_mc_fractions(ctx, n, _ptr(tallies), _ptr(rat, torch.float32, 3 * n), _stream(stream)))
+
+
+def fos_mc_execute_weighted(ctx, seed: int, tallies, launch=None, stream=None) -> None:
+    n = fos_mc_prepared_items(ctx)
+    _check(ctx, lib().fos_mc_execute_weighted(ctx, c_uint64(seed), _launch(launch),
+                                              _ptr(tallies, None, n * N_TALLY_W) if n else _ptr(tallies),
+                                              _stream(stream)))
+
+
+def fos_mc_run_weighted(ctx, problem: MCProblem, seed: int, tallies, launch=None, stream=None) -> None:
+    _ptr(tallies, None, problem.n_items * N_TALLY_W)
+    _check(ctx, lib().fos_mc_run_weighted(ctx, ctypes.byref(problem.struct), c_uint64(seed), _launch(launch),
+                                          _ptr(tallies), _stream(stream)))
+
+
+def fos_mc_weighted_fractions(ctx, tallies, rat, se=None, stream=None) -> None:
+    import torch
+    n = tallies.numel() // N_TALLY_W
+    _check(ctx, lib().fos_mc_weighted_fractions(ctx, n, _ptr(tallies), _ptr(rat, torch.float32, 3 * n),
+                                                _ptr(se, torch.float32, 3 * n), _stream(stream)))
 
 
 def fos_mc_prepared_items(ctx) -> int:

@@ -116,7 +116,7 @@ def training_recipe_id(seed: int) -> str:
     return h.hexdigest()[:16]
 
 
-def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 250_000, log=None, label: bool = True):
+def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True):
     """n single-layer items labelled by the walk at `photons` each.
     Returns (x [n*8], y [n*3], photon-steps, seconds).  With label=False only
     the features are made (y is None): the items are a function of

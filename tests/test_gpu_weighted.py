@@ -1,0 +1,163 @@
+"""GPU weighted-packet walk (fos_mc_run_weighted) against the oracle's
+weighted walk: statistical parity with independent seeds (4 combined
+standard errors from each side's own variance estimate), same-seed coupling,
+closed forms, exact lossless bookkeeping, launch-independence and the
+photon-budget limit; and the variance / cost comparison with the analog
+walk that the weighted form is for."""
+import numpy as np
+import pytest
+
+from gpu_helpers import device_problem, make_arrays, run_gpu
+from test_oracle_walk import _adding_stack
+
+pytestmark = pytest.mark.gpu
+
+UNIT = float(1 << 36)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_2409_00165_amd import fos
+    c = fos.Context(0)
+    yield c.handle
+    c.close()
+
+
+def _gpu_w(ctx, torch, a, seed, launch=None):
+    """tallies int64 [I, 11], fractions [I, 3], standard errors [I, 3]."""
+    from paper_2409_00165_amd import fos
+    prob = device_problem(a)
+    tal = torch.full((prob.n_items * fos.N_TALLY_W,), -1, dtype=torch.int64, device="cuda")
+    fos.fos_mc_run_weighted(ctx, prob, seed, tal, launch=launch)
+    rat = torch.zeros(3 * prob.n_items, device="cuda")
+    se = torch.zeros(3 * prob.n_items, device="cuda")
+    fos.fos_mc_weighted_fractions(ctx, tal, rat, se)
+    torch.cuda.synchronize()
+    I = prob.n_items
+    return (tal.cpu().numpy().reshape(I, fos.N_TALLY_W), rat.cpu().numpy().reshape(I, 3).astype(np.float64),
+            se.cpu().numpy().reshape(I, 3).astype(np.float64))
+
+
+def _orc_w(orc, a, seed):
+    f = lambda k: np.asarray(a[k], np.float64)
+    o, st = orc.walk_weighted_batch(a["n_layers"], f("mu_s"), f("mu_a"), f("g"), f("n_layer"), f("thickness"),
+                                    f("n_upper"), f("n_lower"), f("k_lower"), f("mu0"),
+                                    np.asarray(a["photons"], np.uint64), seed=seed)
+    N = np.asarray(a["photons"], np.float64)[:, None]
+    mean = np.stack([o[:, 0] + o[:, 1], o[:, 2], o[:, 3]], 1) / N
+    m1 = np.stack([o[:, 1], o[:, 2], o[:, 3]], 1) / N
+    m2 = np.stack([o[:, 4], o[:, 5], o[:, 6]], 1) / N
+    se = np.sqrt(np.maximum(m2 - m1 ** 2, 0.0) / N)
+    return o, st, mean, se
+
+
+def _mixed_items(photons):
+    rng = np.random.default_rng(31)
+    I = 12
+    mus = np.exp(rng.uniform(np.log(0.05), np.log(20.0), I))
+    mua = np.exp(rng.uniform(np.log(1e-3), np.log(1.0), I))
+    g = rng.uniform(-0.3, 0.95, I)
+    n = rng.uniform(1.0, 1.7, I)
+    t = rng.uniform(1.0, 20.0, I)
+    a = make_arrays(mus[:, None], mua[:, None], g[:, None], n[:, None], t[:, None], photons=photons)
+    a["mu0"] = rng.uniform(0.5, 1.0, I).astype(np.float32)
+    a["n_lower"] = np.where(rng.uniform(size=I) < 0.5, 1.0, 3.5).astype(np.float32)
+    a["k_lower"] = np.where(a["n_lower"] > 2, 0.01, 0.0).astype(np.float32)
+    return a
+
+
+def test_weighted_matches_oracle_statistically(ctx, torch, orc):
+    a = _mixed_items(200_000)
+    _, got, se_g = _gpu_w(ctx, torch, a, seed=101)
+    _, _, ref, se_o = _orc_w(orc, a, seed=202)
+    z = np.abs(got - ref) / np.sqrt(se_g ** 2 + se_o ** 2 + 1e-30)
+    print("weighted GPU vs oracle, worst z:", z.max(), flush=True)
+    assert (z <= 4.0).all(), (got, ref, z)
+
+
+def test_weighted_same_seed_tracks_the_oracle(ctx, torch, orc):
+    # same counters, same decisions: FP32 vs FP64 differ only by rare flips
+    a = _mixed_items(50_000)
+    _, got, _ = _gpu_w(ctx, torch, a, seed=7)
+    _, _, ref, _ = _orc_w(orc, a, seed=7)
+    d = np.abs(got - ref).max()
+    print("weighted same-seed max |d|:", d, flush=True)
+    assert d < 2e-3
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=[1.5], t=[50.0], mua=[0.01]),
+    dict(n=[1.4, 1.7, 1.5], t=[10.0, 25.0, 5.0], mua=[0.01, 0.0, 0.04], n_lower=3.5, k_lower=0.01, mu0=0.8),
+])
+def test_weighted_non_scattering_closed_form(ctx, torch, case):
+    n, t, mua = case["n"], case["t"], case["mua"]
+    L = len(n)
+    kw = {k: case[k] for k in ("n_lower", "k_lower", "mu0") if k in case}
+    a = make_arrays([[0.0] * L], [mua], [[0.0] * L], [n], [t], photons=400_000, **kw)
+    tal, got, se = _gpu_w(ctx, torch, a, seed=3)
+    ps = _adding_stack(n, t, mua, 1.0, kw.get("n_lower", 1.0), kw.get("k_lower", 0.0), kw.get("mu0", 1.0))
+    ref = np.array([ps[0] + ps[1], ps[2], ps[3]])
+    assert (np.abs(got[0] - ref) <= 4 * se[0] + 2e-6).all(), (got, ref, se)
+    assert tal[0, 7] == 0                      # no roulette without scattering
+
+
+def test_weighted_lossless_keeps_every_packet(ctx, torch):
+    a = make_arrays([[1.0]], [[0.0]], [[0.6]], [[1.5]], [[10.0]], photons=30_000, n_lower=1.3)
+    tal, got, _ = _gpu_w(ctx, torch, a, seed=5)
+    N = 30_000
+    assert tal[0, 2] == 0 and tal[0, 5] == 0 and tal[0, 7] == 0 and tal[0, 8] == 0
+    assert tal[0, 10] == N
+    # specular R0 and the entering packet 1 - R0 (an FP32 difference) sum to one
+    # photon up to the packet's FP32 rounding
+    total = int(tal[0, 0]) + int(tal[0, 1]) + int(tal[0, 3])
+    assert abs(total - N * UNIT) <= N * UNIT * 1e-7
+
+
+def test_weighted_independent_of_launch(ctx, torch):
+    a = _mixed_items(30_000)
+    base, _, _ = _gpu_w(ctx, torch, a, seed=9)
+    for launch in ({"block_size": 128, "chunk": 333, "refill_min": 1}, {"block_size": 512, "chunk": 65536},
+                   {"blocks_per_cu": 1, "refill_min": 32}):
+        t, _, _ = _gpu_w(ctx, torch, a, seed=9, launch=launch)
+        assert np.array_equal(t, base), launch
+
+
+def test_weighted_rejects_budgets_beyond_the_weight_units(ctx, torch):
+    from paper_2409_00165_amd import fos
+    a = make_arrays([[1.0]], [[0.1]], [[0.5]], [[1.5]], [[5.0]], photons=(1 << 27) + 1)
+    prob = device_problem(a)
+    tal = torch.zeros(fos.N_TALLY_W, dtype=torch.int64, device="cuda")
+    with pytest.raises(fos.FosError) as ei:
+        fos.fos_mc_run_weighted(ctx, prob, 1, tal)
+    assert ei.value.status_name == "FOS_E_UNSUPPORTED"
+
+
+def test_weighted_and_analog_estimate_the_same_and_report_efficiency(ctx, torch):
+    """Both walks estimate the same R, A, T; the weighted one's A has a
+    smaller variance per photon in scattering, weakly absorbing media, at a
+    higher step count.  Efficiency = 1 / (variance per photon x steps per
+    photon) is printed for both."""
+    a = make_arrays([[5.0], [2.0], [1.0]], [[0.005], [0.05], [0.5]], [[0.8], [0.5], [0.0]], [[1.5]] * 3,
+                    [[20.0], [10.0], [5.0]], photons=200_000)
+    N = 200_000
+    tw, gw, sew = _gpu_w(ctx, torch, a, seed=41)
+    ta = run_gpu(ctx, a, seed=42)
+    pa = np.stack([ta[:, 0] + ta[:, 1], ta[:, 2], ta[:, 3]], 1) / N
+    sea = np.sqrt(pa * (1 - pa) / N)
+    z = np.abs(gw - pa) / np.sqrt(sew ** 2 + sea ** 2 + 1e-30)
+    assert (z <= 4.0).all(), (gw, pa, z)
+    steps_w = tw[:, 9] / N
+    steps_a = ta[:, 5] / N
+    var_w = sew[:, 1] ** 2 * N
+    var_a = sea[:, 1] ** 2 * N
+    eff_ratio = (var_a * steps_a) / (var_w * steps_w)
+    print("A variance per photon weighted/analog:", var_w / var_a, "steps weighted/analog:", steps_w / steps_a,
+          "efficiency weighted/analog:", eff_ratio, flush=True)
+    assert var_w[0] < var_a[0]                 # weakly absorbing, strongly scattering

@@ -481,6 +481,73 @@ def context_main(args):
     return 0
 
 
+def weighted_main(args):
+    """Analog against weighted-packet walk on the two-species 500-wavelength
+    slab: throughput of each, and the efficiency of the absorptance estimate,
+    1 / (variance per photon x photon-steps per photon), per wavelength."""
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    wl = W.two_species_500(photons=args.photons)
+    prob, _ = gpu_problem(h, wl)
+    n = wl.n_items
+    N = float(args.photons)
+    out = {}
+    for name, nt, run in (("analog", fos.N_TALLY, fos.fos_mc_run), ("weighted", fos.N_TALLY_W, fos.fos_mc_run_weighted)):
+        tal = torch.zeros(n * nt, dtype=torch.int64, device="cuda")
+        for _ in range(args.warmup):
+            run(h, prob, args.seed, tal)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            run(h, prob, args.seed + k, tal)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        t = tal.view(n, nt).cpu().numpy().astype(np.float64)
+        if name == "analog":
+            steps = t[:, 5]
+            a = t[:, 2] / N
+            var_a = a * (1 - a)                             # per photon
+        else:
+            steps = t[:, 9]
+            u = fos.WEIGHT_UNIT
+            a = t[:, 2] / u / N
+            var_a = np.maximum(t[:, 5] / u / N - a * a, 0.0)
+        out[name] = {"seconds": dt, "photon_steps_per_s": steps.sum() / dt, "steps_per_photon": steps / N,
+                     "A": a, "var_A_per_photon": var_a}
+        say(f"{name}: {dt * 1e3:.1f} ms per step, {steps.sum() / dt:.3e} photon-steps/s, "
+            f"{steps.sum() / N / n:.1f} steps per photon")
+    an, wt = out["analog"], out["weighted"]
+    ok = (an["var_A_per_photon"] > 0) & (wt["var_A_per_photon"] > 0)
+    eff = (an["var_A_per_photon"] * an["steps_per_photon"])[ok] / (wt["var_A_per_photon"] * wt["steps_per_photon"])[ok]
+    se = np.sqrt(an["var_A_per_photon"] / N + wt["var_A_per_photon"] / N)
+    z = np.abs(an["A"] - wt["A"]) / np.maximum(se, 1e-30)
+    rec = {"metric": "photon-steps/s of the weighted-packet walk, and its A-estimate efficiency against the analog "
+                     "walk (two-species 500-wavelength slab)",
+           "value": wt["photon_steps_per_s"], "unit": "photon-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * wt["seconds"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"two_species_500, {args.photons} photons per wavelength", "items": n},
+           "analog_photon_steps_per_s": an["photon_steps_per_s"],
+           "steps_per_photon": {"analog": float(an["steps_per_photon"].mean()),
+                                "weighted": float(wt["steps_per_photon"].mean())},
+           "efficiency_weighted_over_analog_A": {"median": float(np.median(eff)), "min": float(eff.min()),
+                                                 "max": float(eff.max()), "wavelengths": int(ok.sum())},
+           "A_agreement_max_z": float(z.max()),
+           "wall_s": time.perf_counter() - t_start}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     print("[bench] start", file=sys.stderr, flush=True)
     ap = argparse.ArgumentParser()
@@ -493,10 +560,11 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
     ap.add_argument("--workload", default="two_species_500",
-                    choices=["two_species_500", "stacks_3layer", "surrogate", "paper_context"],
+                    choices=["two_species_500", "stacks_3layer", "surrogate", "paper_context", "weighted"],
                     help="two_species_500 (default, the headline line), stacks_3layer (batched sweep), "
                          "surrogate (training on walk labels + design sweep with Monte Carlo fallback) or "
-                         "paper_context (a run shaped like the paper's desktop timing, GPU and oracle)")
+                         "paper_context (a run shaped like the paper's desktop timing, GPU and oracle) or "
+                         "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-photons", type=int, default=100_000)
     ap.add_argument("--epochs", type=int, default=60)
@@ -527,6 +595,8 @@ def main(argv=None):
         return sweep_main(args)
     if args.workload == "paper_context":
         return context_main(args)
+    if args.workload == "weighted":
+        return weighted_main(args)
 
     import torch
     from paper_2409_00165_amd import fos

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define FOS_ABI_VERSION 1
+#define FOS_ABI_VERSION 2
 #define FOS_MAX_LAYERS 8
 
 /* tally slots per item, in this order, uint64 each */
@@ -239,6 +239,16 @@ typedef struct {
     const double* k_p;
     const double* r;          /* micrometres */
     const double* f;
+    /* optional per-entry arrays (NULL = none), Scattering properties section
+     * and supplementary eqs. (S1)-(S9): */
+    const double* sd;         /* standard deviation of the diameter 2r (micrometres): the entry becomes 101
+                                 diameters evenly over 2r - 3 sd .. 2r + 3 sd with Gaussian weights,
+                                 renormalised over the positive ones, as volume fractions f w; 0 = one size */
+    const double* r_core;     /* core radius (micrometres), 0 <= r_core <= r: > 0 makes the entry a coated
+                                 sphere, core n_core + i k_core inside a shell n_p + i k_p out to r (cross
+                                 sections and eqs. (13)-(16) use r); not combined with sd > 0 */
+    const double* n_core;
+    const double* k_core;
 } fos_optics_problem;
 
 /* Effective mu_s, mu_a (1/micrometre) and g of every cell: Lorenz-Mie

@@ -74,6 +74,16 @@ def _load():
         lib.orc_layer_optics.argtypes = [c_double, c_double, c_double, c_int, d, d, d, d, d]
         lib.orc_optics_batch.argtypes = [c_int, d, d, d, POINTER(c_int64), d, d, d, d, c_int, d]
         lib.orc_optics_batch.restype = c_int
+        lib.orc_optics_batch_ex.argtypes = [c_int, d, d, d, POINTER(c_int64), d, d, d, d, d, d, d, d, c_int, d]
+        lib.orc_optics_batch_ex.restype = c_int
+        lib.orc_mie_coated_coeffs.argtypes = [c_double] * 8 + [c_int, d, d]
+        lib.orc_mie_coated_coeffs.restype = c_int
+        lib.orc_mie_coated.argtypes = [c_double] * 9 + [d]
+        lib.orc_mie_coated.restype = c_int
+        lib.orc_gaussian_sizes.argtypes = [c_double, c_double, d, d]
+        lib.orc_gaussian_sizes.restype = c_int
+        lib.orc_layer_optics_ex.argtypes = [c_double, c_double, c_double, c_int] + [d] * 9
+        lib.orc_layer_optics_ex.restype = c_int
         _lib = lib
     return _lib
 
@@ -211,6 +221,48 @@ def mie_sphere(lam, n_m, k_m, n_p, k_p, r):
     return o[0], o[1], o[2], int(o[3])
 
 
+def mie_coated_coeffs(x, y, m1, m2, nmax):
+    """a_n, b_n (n = 1..nmax) of a coated sphere, supplementary eqs. (S1)-(S4);
+    x, y, m1, m2 complex.  Raises if the literal form overflowed."""
+    a = np.zeros(2 * nmax)
+    b = np.zeros(2 * nmax)
+    x, y, m1, m2 = complex(x), complex(y), complex(m1), complex(m2)
+    rc = _load().orc_mie_coated_coeffs(x.real, x.imag, y.real, y.imag, m1.real, m1.imag, m2.real, m2.imag, nmax,
+                                       _dp(a), _dp(b))
+    if rc != 0:
+        raise FloatingPointError("coated-sphere coefficients overflowed")
+    return a[0::2] + 1j * a[1::2], b[0::2] + 1j * b[1::2]
+
+
+def mie_coated(lam, n_m, k_m, n_core, k_core, r_core, n_shell, k_shell, r):
+    """(q_ext, q_sca, g, nmax) of a coated sphere referred to its outer radius r."""
+    o = np.zeros(4)
+    rc = _load().orc_mie_coated(lam, n_m, k_m, n_core, k_core, r_core, n_shell, k_shell, r, _dp(o))
+    if rc != 0:
+        raise FloatingPointError("coated-sphere coefficients overflowed")
+    return o[0], o[1], o[2], int(o[3])
+
+
+def gaussian_sizes(D, sd):
+    """The paper's 101-size Gaussian diameter spread: (radii, weights)."""
+    r = np.zeros(101)
+    w = np.zeros(101)
+    k = _load().orc_gaussian_sizes(D, sd, _dp(r), _dp(w))
+    return r[:k].copy(), w[:k].copy()
+
+
+def layer_optics_ex(lam, n_m, k_m, n_p, k_p, r, f, sd=None, r_core=None, n_core=None, k_core=None):
+    """layer_optics with optional diameter spreads and cores (None = none)."""
+    n_p, k_p, r, f = (_f64(np.atleast_1d(x)) for x in (n_p, k_p, r, f))
+    opt = [None if a is None else _f64(np.atleast_1d(a)) for a in (sd, r_core, n_core, k_core)]
+    o = np.zeros(3)
+    rc = _load().orc_layer_optics_ex(lam, n_m, k_m, len(n_p), _dp(n_p), _dp(k_p), _dp(r), _dp(f),
+                                     *[None if a is None else _dp(a) for a in opt], _dp(o))
+    if rc != 0:
+        raise FloatingPointError("coated-sphere coefficients overflowed")
+    return o[0], o[1], o[2]
+
+
 def layer_optics(lam, n_m, k_m, n_p, k_p, r, f):
     """(mu_s, mu_a, g) of one layer at one wavelength, eqs. (13)-(20)."""
     n_p, k_p, r, f = (_f64(np.atleast_1d(x)) for x in (n_p, k_p, r, f))
@@ -220,14 +272,20 @@ def layer_optics(lam, n_m, k_m, n_p, k_p, r, f):
 
 
 def optics_batch(req, n_threads=None):
-    """Optics of every cell of a workloads.optics_request(); returns [C, 3]."""
+    """Optics of every cell of a workloads.optics_request(); returns [C, 3].
+    Optional request arrays sd, r_core, n_core, k_core (per particle entry)
+    add diameter spreads and cores."""
     C = int(req["cells"])
     out = np.zeros((C, 3))
     offs = np.ascontiguousarray(req["offsets"], np.int64)
     arrs = [_f64(req[k]) for k in ("lam", "n_m", "k_m")]
     parts = [_f64(req[k]) for k in ("n_p", "k_p", "r", "f")]
-    _load().orc_optics_batch(C, *[_dp(a) for a in arrs], offs.ctypes.data_as(POINTER(c_int64)),
-                             *[_dp(a) for a in parts], n_threads or default_threads(), _dp(out))
+    opt = [None if req.get(k) is None else _f64(req[k]) for k in ("sd", "r_core", "n_core", "k_core")]
+    rc = _load().orc_optics_batch_ex(C, *[_dp(a) for a in arrs], offs.ctypes.data_as(POINTER(c_int64)),
+                                     *[_dp(a) for a in parts], *[None if a is None else _dp(a) for a in opt],
+                                     n_threads or default_threads(), _dp(out))
+    if rc != 0:
+        raise FloatingPointError("coated-sphere coefficients overflowed")
     return out
 
 

@@ -23,7 +23,9 @@
  *     instead of the garbled closed forms (6)-(9); cross sections eqs.
  *     (10)-(12); asymmetry eq. (15); effective medium eqs. (13), (14), (16);
  *     clamp, dependent-scattering correction eqs. (17)-(19) and matrix
- *     absorption eq. (20).
+ *     absorption eq. (20); coated (core-shell) spheres by supplementary eqs.
+ *     (S1)-(S9) and the 101-size Gaussian diameter spread of the
+ *     Scattering-properties section.
  *
  * Everything is double precision.  Complex arithmetic uses C99 <complex.h>.
  */
@@ -633,6 +635,150 @@ int orc_mie_sphere(double lam, double nm, double km, double np_, double kp, doub
     return 0;
 }
 
+/* --- coated (core-shell) spheres, supplementary eqs. (S1)-(S9) ------------- */
+/* Riccati-Bessel psi_n(z) = z j_n(z) (eq. (S7)), n = 0..nmax: upward
+ * recurrence while n <= |z|, above that from the logarithmic derivative,
+ * psi_n = psi_{n-1} / (D_n + n/z) (the upward form loses accuracy there). */
+static void riccati_psi(double complex z, int nmax, double complex* psi)
+{
+    double complex* D = (double complex*)malloc(sizeof(double complex) * (nmax + 1));
+    log_derivative(z, nmax, D);
+    double az = cabs(z);
+    double complex pm1 = ccos(z);
+    psi[0] = csin(z);
+    for (int n = 1; n <= nmax; ++n) {
+        psi[n] = (n <= az) ? (2.0 * n - 1.0) / z * psi[n - 1] - (n == 1 ? pm1 : psi[n - 2])
+                           : psi[n - 1] / (D[n] + n / z);
+    }
+    free(D);
+}
+
+/* chi_n(z) = z y_n(z) (eq. (S8)), n = 0..nmax, by the upward recurrence,
+ * stable for this growing solution: chi_0 = -cos z, chi_1 = -cos z / z - sin z. */
+static void riccati_chi(double complex z, int nmax, double complex* chi)
+{
+    chi[0] = -ccos(z);
+    if (nmax >= 1) chi[1] = -ccos(z) / z - csin(z);
+    for (int n = 2; n <= nmax; ++n) chi[n] = (2.0 * n - 1.0) / z * chi[n - 1] - chi[n - 2];
+}
+
+/* derivative of a Riccati-Bessel function: f'_n(z) = f_{n-1}(z) - (n/z) f_n(z) */
+static double complex rb_deriv(const double complex* f, int n, double complex z)
+{
+    return f[n - 1] - (double)n / z * f[n];
+}
+
+/* Mie coefficients of a coated sphere, written out as eqs. (S1)-(S4): core
+ * size parameter x = k r_core and outer y = k r_outer (k the host wave number,
+ * complex in an absorbing host), m1 = core / host, m2 = shell / host (S5, S6),
+ * xi_n = psi_n + i chi_n (S9, first-kind Hankel).  n = 1..nmax.  Meant for
+ * moderate sizes (the literal form lets chi_n grow without bound). */
+int orc_mie_coated_coeffs(double xr, double xi_, double yr, double yi, double m1r, double m1i, double m2r,
+                          double m2i, int nmax, double* a_out, double* b_out)
+{
+    if (nmax < 1) return -1;
+    double complex x = xr + I * xi_, y = yr + I * yi;
+    double complex m1 = m1r + I * m1i, m2 = m2r + I * m2i;
+    size_t sz = sizeof(double complex) * (nmax + 1);
+    double complex *p1x = malloc(sz), *p2x = malloc(sz), *c2x = malloc(sz), *p2y = malloc(sz), *c2y = malloc(sz);
+    double complex *py = malloc(sz), *cy = malloc(sz);
+    riccati_psi(m1 * x, nmax, p1x);
+    riccati_psi(m2 * x, nmax, p2x);
+    riccati_chi(m2 * x, nmax, c2x);
+    riccati_psi(m2 * y, nmax, p2y);
+    riccati_chi(m2 * y, nmax, c2y);
+    riccati_psi(y, nmax, py);
+    riccati_chi(y, nmax, cy);
+    int bad = 0;
+    for (int n = 1; n <= nmax; ++n) {
+        double complex dp1x = rb_deriv(p1x, n, m1 * x), dp2x = rb_deriv(p2x, n, m2 * x);
+        double complex dc2x = rb_deriv(c2x, n, m2 * x), dp2y = rb_deriv(p2y, n, m2 * y);
+        double complex dc2y = rb_deriv(c2y, n, m2 * y), dpy = rb_deriv(py, n, y), dcy = rb_deriv(cy, n, y);
+        double complex xin = py[n] + I * cy[n], dxin = dpy + I * dcy;
+        /* (S3), (S4) */
+        double complex An = (m2 * p2x[n] * dp1x - m1 * dp2x * p1x[n]) / (m2 * c2x[n] * dp1x - m1 * dc2x * p1x[n]);
+        double complex Bn = (m2 * p1x[n] * dp2x - m1 * p2x[n] * dp1x) / (m2 * dc2x * p1x[n] - m1 * dp1x * c2x[n]);
+        /* (S1), (S2) */
+        double complex ua = dp2y - An * dc2y, va = p2y[n] - An * c2y[n];
+        double complex ub = dp2y - Bn * dc2y, vb = p2y[n] - Bn * c2y[n];
+        double complex an = (py[n] * ua - m2 * dpy * va) / (xin * ua - m2 * dxin * va);
+        double complex bn = (m2 * py[n] * ub - dpy * vb) / (m2 * xin * ub - dxin * vb);
+        if (!isfinite(cabs(an)) || !isfinite(cabs(bn))) bad = 1;
+        a_out[2 * (n - 1)] = creal(an); a_out[2 * (n - 1) + 1] = cimag(an);
+        b_out[2 * (n - 1)] = creal(bn); b_out[2 * (n - 1) + 1] = cimag(bn);
+    }
+    free(p1x); free(p2x); free(c2x); free(p2y); free(c2y); free(py); free(cy);
+    return bad ? -2 : 0;
+}
+
+/* Efficiencies of a coated sphere (core radius rc, index nc + i kc; shell to
+ * radius r, index ns + i ks) in host nm + i km: eqs. (11), (12), (15) with the
+ * coefficients of (S1)-(S4), the cross sections referred to the outer radius,
+ * and alpha of eq. (10) from the outer radius.  The series length is eq. (12)
+ * with |y| the larger of the core's and the shell's size parameters.
+ * out = q_ext, q_sca, g, nmax; returns < 0 if the literal form overflowed. */
+int orc_mie_coated(double lam, double nm, double km, double nc, double kc, double rc, double ns, double ks,
+                   double r, double* out)
+{
+    double complex Nm = nm + I * km, Nc = nc + I * kc, Ns = ns + I * ks;
+    double complex x = 2.0 * M_PI * rc * Nm / lam, y = 2.0 * M_PI * r * Nm / lam;
+    double yabs = fmax(2.0 * M_PI * r * cabs(Ns) / lam, 2.0 * M_PI * rc * cabs(Nc) / lam);
+    int nmax = orc_mie_nmax(yabs);
+    int nn = nmax + 1;
+    double* a = (double*)malloc(sizeof(double) * 2 * nn);
+    double* b = (double*)malloc(sizeof(double) * 2 * nn);
+    double complex m1 = Nc / Nm, m2 = Ns / Nm;
+    int rc_ = orc_mie_coated_coeffs(creal(x), cimag(x), creal(y), cimag(y), creal(m1), cimag(m1), creal(m2),
+                                    cimag(m2), nn, a, b);
+    double sext = 0.0, ssca = 0.0, sg = 0.0;
+    double complex iNm2 = 1.0 / (Nm * Nm);
+    for (int n = 1; n <= nmax; ++n) {
+        double complex an = a[2 * (n - 1)] + I * a[2 * (n - 1) + 1];
+        double complex bn = b[2 * (n - 1)] + I * b[2 * (n - 1) + 1];
+        double complex an1 = a[2 * n] + I * a[2 * n + 1];
+        double complex bn1 = b[2 * n] + I * b[2 * n + 1];
+        sext += (2.0 * n + 1.0) * creal((an + bn) * iNm2);
+        ssca += (2.0 * n + 1.0) * (creal(an * conj(an)) + creal(bn * conj(bn)));
+        sg += (double)n * (n + 2.0) / (n + 1.0) * creal(an * conj(an1) + bn * conj(bn1))
+            + (2.0 * n + 1.0) / ((double)n * (n + 1.0)) * creal(an * conj(bn));
+    }
+    double alpha = 4.0 * M_PI * r * km / lam;
+    double gam = orc_gamma(alpha);
+    double cext = lam * lam / (2.0 * M_PI) * sext;
+    double csca = lam * lam * exp(-alpha) / (2.0 * M_PI * gam * creal(Nm * conj(Nm))) * ssca;
+    double area = M_PI * r * r;
+    out[0] = cext / area;
+    out[1] = csca / area;
+    out[2] = ssca > 0.0 ? 2.0 * sg / ssca : 0.0;
+    out[3] = (double)nmax;
+    free(a); free(b);
+    return rc_;
+}
+
+/* The paper's size-distribution option: one diameter D with standard
+ * deviation sd becomes 101 diameters evenly spaced over D - 3 sd .. D + 3 sd
+ * with Gaussian weights, renormalised to sum to one (read as volume-fraction
+ * weights, like the per-size fractions of a custom distribution); diameters
+ * that are not positive are left out.  Writes radii and weights, returns the
+ * number of sizes (1 when sd = 0). */
+int orc_gaussian_sizes(double D, double sd, double* r_out, double* w_out)
+{
+    if (!(sd > 0.0)) { r_out[0] = 0.5 * D; w_out[0] = 1.0; return 1; }
+    int k = 0;
+    double sum = 0.0;
+    for (int j = 0; j <= 100; ++j) {
+        double d = D - 3.0 * sd + 6.0 * sd * j / 100.0;
+        if (!(d > 0.0)) continue;
+        double z = (d - D) / sd;
+        r_out[k] = 0.5 * d;
+        w_out[k] = exp(-0.5 * z * z);
+        sum += w_out[k];
+        ++k;
+    }
+    for (int j = 0; j < k; ++j) w_out[j] /= sum;
+    return k;
+}
+
 /* Effective medium of one layer at one wavelength, eqs. (13)-(20).
  * Particles i = 0..np-1 with index np_[i] + i kp[i], radius r[i], volume
  * fraction f[i].  Outputs out[0] = mu_s, out[1] = mu_a (total, eq. (20)),
@@ -642,19 +788,41 @@ int orc_mie_sphere(double lam, double nm, double km, double np_, double kp, doub
  * Negative summed coefficients are set to zero; when the total volume
  * fraction exceeds 0.08 both are multiplied by
  * C = 1 + 1.5 F - 0.75 F^2, F = sum f_i; finally the matrix absorption
- * 4 pi k_m (1 - F) / lambda is added to mu_a. */
-int orc_layer_optics(double lam, double nm, double km, int np, const double* np_, const double* kp,
-                     const double* r, const double* f, double* out)
+ * 4 pi k_m (1 - F) / lambda is added to mu_a.
+ * Optional per-particle arrays (NULL = none): sd, the standard deviation of
+ * the diameter 2 r (the particle becomes orc_gaussian_sizes(); r is its mean
+ * radius); rc, nc, kc, a core of radius rc > 0 and index nc + i kc inside a
+ * shell of index n_p + i k_p out to r (no size spread for coated spheres, as
+ * in the paper).  Returns < 0 if a coated sphere overflowed the literal form. */
+int orc_layer_optics_ex(double lam, double nm, double km, int np, const double* np_, const double* kp,
+                        const double* r, const double* f, const double* sd, const double* rc,
+                        const double* nc, const double* kc, double* out)
 {
     double mus = 0.0, mua = 0.0, gs = 0.0, F = 0.0;
+    double rr[101], ww[101];
+    int status = 0;
     for (int i = 0; i < np; ++i) {
-        double q[4];
-        orc_mie_sphere(lam, nm, km, np_[i], kp[i], r[i], q);
-        double ws = 1.5 * q[1] * f[i] / (2.0 * r[i]);
-        mus += ws;
-        mua += 1.5 * (q[0] - q[1]) * f[i] / (2.0 * r[i]);
-        gs += ws * q[2];
         F += f[i];
+        if (rc && rc[i] > 0.0) {
+            /* a coated sphere: core rc, shell out to r (no size spread) */
+            double q[4];
+            if (orc_mie_coated(lam, nm, km, nc[i], kc[i], rc[i], np_[i], kp[i], r[i], q) < 0) status = -2;
+            double ws = 1.5 * q[1] * f[i] / (2.0 * r[i]);
+            mus += ws;
+            mua += 1.5 * (q[0] - q[1]) * f[i] / (2.0 * r[i]);
+            gs += ws * q[2];
+            continue;
+        }
+        int k = orc_gaussian_sizes(2.0 * r[i], sd ? sd[i] : 0.0, rr, ww);
+        for (int j = 0; j < k; ++j) {
+            double q[4];
+            orc_mie_sphere(lam, nm, km, np_[i], kp[i], rr[j], q);
+            double fj = f[i] * ww[j];
+            double ws = 1.5 * q[1] * fj / (2.0 * rr[j]);
+            mus += ws;
+            mua += 1.5 * (q[0] - q[1]) * fj / (2.0 * rr[j]);
+            gs += ws * q[2];
+        }
     }
     double g = mus > 0.0 ? gs / mus : 0.0;
     if (mus < 0.0) mus = 0.0;
@@ -666,7 +834,13 @@ int orc_layer_optics(double lam, double nm, double km, int np, const double* np_
     }
     mua += 4.0 * M_PI * km * (1.0 - F) / lam;
     out[0] = mus; out[1] = mua; out[2] = g;
-    return 0;
+    return status;
+}
+
+int orc_layer_optics(double lam, double nm, double km, int np, const double* np_, const double* kp,
+                     const double* r, const double* f, double* out)
+{
+    return orc_layer_optics_ex(lam, nm, km, np, np_, kp, r, f, NULL, NULL, NULL, NULL, out);
 }
 
 /* Many cells (layer x wavelength), CSR particle lists, threaded. */
@@ -675,8 +849,10 @@ typedef struct {
     const double *lam, *nm, *km;
     const int64_t* off;
     const double *np_, *kp, *r, *f;
+    const double *sd, *rc, *nc, *kc;   /* optional, NULL = homogeneous, one size */
     double* out;
     int next;
+    int status;
 } optics_job;
 
 static void* optics_worker(void* arg)
@@ -687,21 +863,31 @@ static void* optics_worker(void* arg)
         if (c >= J->n_cells) break;
         int64_t o = J->off[c];
         int cnt = (int)(J->off[c + 1] - o);
-        orc_layer_optics(J->lam[c], J->nm[c], J->km[c], cnt, J->np_ + o, J->kp + o, J->r + o,
-                         J->f + o, J->out + 3 * (size_t)c);
+        int st = orc_layer_optics_ex(J->lam[c], J->nm[c], J->km[c], cnt, J->np_ + o, J->kp + o, J->r + o,
+                                     J->f + o, J->sd ? J->sd + o : NULL, J->rc ? J->rc + o : NULL,
+                                     J->nc ? J->nc + o : NULL, J->kc ? J->kc + o : NULL, J->out + 3 * (size_t)c);
+        if (st < 0) __atomic_store_n(&J->status, st, __ATOMIC_RELAXED);
     }
     return NULL;
+}
+
+int orc_optics_batch_ex(int n_cells, const double* lam, const double* nm, const double* km,
+                        const int64_t* offsets, const double* np_, const double* kp, const double* r,
+                        const double* f, const double* sd, const double* rc, const double* nc, const double* kc,
+                        int n_threads, double* out)
+{
+    if (n_threads < 1) return -1;
+    optics_job J = {n_cells, lam, nm, km, offsets, np_, kp, r, f, sd, rc, nc, kc, out, 0, 0};
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    for (int k = 0; k < n_threads; ++k) pthread_create(&th[k], NULL, optics_worker, &J);
+    for (int k = 0; k < n_threads; ++k) pthread_join(th[k], NULL);
+    free(th);
+    return J.status;
 }
 
 int orc_optics_batch(int n_cells, const double* lam, const double* nm, const double* km,
                      const int64_t* offsets, const double* np_, const double* kp, const double* r,
                      const double* f, int n_threads, double* out)
 {
-    if (n_threads < 1) return -1;
-    optics_job J = {n_cells, lam, nm, km, offsets, np_, kp, r, f, out, 0};
-    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
-    for (int k = 0; k < n_threads; ++k) pthread_create(&th[k], NULL, optics_worker, &J);
-    for (int k = 0; k < n_threads; ++k) pthread_join(th[k], NULL);
-    free(th);
-    return 0;
+    return orc_optics_batch_ex(n_cells, lam, nm, km, offsets, np_, kp, r, f, NULL, NULL, NULL, NULL, n_threads, out);
 }

@@ -55,7 +55,13 @@ enum OptErrCode : int {
     kOptErrKp = 6,
     kOptErrRadius = 7,
     kOptErrFraction = 8,
+    kOptErrSpread = 9,
+    kOptErrCore = 10,
+    kOptErrSpreadCore = 11,
 };
+// optics_scan flags: some entry has a diameter spread / a core
+constexpr unsigned int kOptHasSpread = 1u, kOptHasCore = 2u;
+constexpr int kSpreadSizes = 101;   // sizes of a Gaussian diameter spread
 
 struct OpticsArgs {
     int n_cells;
@@ -63,8 +69,12 @@ struct OpticsArgs {
     const double *lam, *n_m, *k_m;
     const int64_t* offsets;
     const double *n_p, *k_p, *r, *f;
+    const double *sd, *r_core, *n_core, *k_core;   // optional per entry (null = none)
     int* cell_of;                 // [n_entries]
-    double* mie;                  // [n_entries * 3]: q_ext, q_sca, g
+    double* mie;                  // [n_entries * units * 3]: q_ext, q_sca, g per size unit
+    int units;                    // size units per entry: 1, or kSpreadSizes when any entry has a spread
+    int d_arrays;                 // logarithmic-derivative arrays per thread in scratch: 1, or 3 with cores
+    unsigned int* flags;          // kOptHas* (optics_scan)
     double2* scratch;             // [(nn_cap + 1) * mie threads]
     unsigned int* nmax;           // largest series length + 1
     int nn_cap;

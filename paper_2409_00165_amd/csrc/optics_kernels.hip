@@ -58,6 +58,13 @@ __device__ __forceinline__ void optics_report(unsigned long long* err, int cell,
     atomicMin(err, ((unsigned long long)(uint32_t)cell << 8) | (unsigned long long)code);
 }
 
+// Diameter of size unit `sub` of a Gaussian spread (mean diameter d0,
+// standard deviation sd): 101 diameters evenly over d0 - 3 sd .. d0 + 3 sd.
+__device__ __forceinline__ double spread_diameter(double d0, double sd, int sub)
+{
+    return d0 - 3.0 * sd + 6.0 * sd * (double)sub / (double)(kSpreadSizes - 1);
+}
+
 __global__ void optics_scan(OpticsArgs a)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,100 +78,203 @@ __global__ void optics_scan(OpticsArgs a)
     if (b < 0 || e < b || e > a.n_entries) { optics_report(a.err, c, kOptErrOffsets); return; }
     if (bad) return;
     int nmax = 0;
+    unsigned int flags = 0u;
     const double two_pi = 2.0 * 3.141592653589793;
     for (int64_t j = b; j < e; ++j) {
         const double np_ = a.n_p[j], kp = a.k_p[j], r = a.r[j], f = a.f[j];
+        const double sd = a.sd ? a.sd[j] : 0.0;
+        const double rc = a.r_core ? a.r_core[j] : 0.0;
         if (!(np_ > 0.0) || !isfinite(np_)) { optics_report(a.err, c, kOptErrNp); return; }
         if (!(kp >= 0.0) || !isfinite(kp)) { optics_report(a.err, c, kOptErrKp); return; }
         if (!(r > 0.0) || !isfinite(r)) { optics_report(a.err, c, kOptErrRadius); return; }
         if (!(f >= 0.0) || !isfinite(f)) { optics_report(a.err, c, kOptErrFraction); return; }
+        if (!(sd >= 0.0) || !isfinite(sd)) { optics_report(a.err, c, kOptErrSpread); return; }
+        if (!(rc >= 0.0) || !(rc <= r)) { optics_report(a.err, c, kOptErrCore); return; }
+        if (sd > 0.0 && rc > 0.0) { optics_report(a.err, c, kOptErrSpreadCore); return; }
         a.cell_of[j] = c;
-        const double ay = two_pi * r * sqrt(np_ * np_ + kp * kp) / lam;   // |y| of eq. (1)
+        // |y| of eq. (1) for the largest size of the entry, at the larger index
+        double ay = two_pi * (sd > 0.0 ? 0.5 * spread_diameter(2.0 * r, sd, kSpreadSizes - 1) : r) *
+                    sqrt(np_ * np_ + kp * kp) / lam;
+        if (rc > 0.0) {
+            const double nc = a.n_core[j], kc = a.k_core[j];
+            if (!(nc > 0.0) || !isfinite(nc) || !(kc >= 0.0) || !isfinite(kc)) {
+                optics_report(a.err, c, kOptErrCore);
+                return;
+            }
+            ay = fmax(ay, two_pi * rc * sqrt(nc * nc + kc * kc) / lam);
+            flags |= kOptHasCore;
+        }
+        if (sd > 0.0) flags |= kOptHasSpread;
         const int nn = series_length(ay) + 1;
         if (nn > nmax) nmax = nn;
     }
     if (nmax > 0) atomicMax(a.nmax, (unsigned int)nmax);
+    if (flags) atomicOr(a.flags, flags);
 }
 
-__global__ void mie_entries(OpticsArgs a)
+// D_n(z), n = 1..nn, by downward recurrence from far above, stored strided
+// (D[n * stride]); returns D_0 as well (from the n = 1 step).
+__device__ cd log_derivative_strided(cd z, int nn, double az, cd* D, size_t stride)
+{
+    int nstart = nn;
+    if (ceil(az) > nstart) nstart = (int)ceil(az);
+    nstart += 16;
+    const cd iz = recip(z);
+    cd d = mk(0.0, 0.0);
+    for (int n = nstart; n > nn; --n) {
+        const cd nz = (double)n * iz;
+        d = nz - recip(d + nz);
+    }
+    D[(size_t)nn * stride] = d;
+    for (int n = nn; n >= 1; --n) {
+        const cd nz = (double)n * iz;
+        d = nz - recip(d + nz);
+        if (n >= 2) D[(size_t)(n - 1) * stride] = d;
+    }
+    return d;   // D_0
+}
+
+// Efficiency series of one sphere (homogeneous, or coated when Nc is given):
+// sext, ssca, sg of eqs. (11), (12), (15).  A coated sphere (core radius rc,
+// index Nc, inside a shell Ns out to r) enters through the logarithmic form of
+// eqs. (S1)-(S4): with D = psi'/psi and G = chi'/chi of the core and shell
+// arguments, T = psi/chi, and
+//   U = (m2 D(m1x) - m1 D(m2x)) / (m2 D(m1x) - m1 G(m2x)) T(m2x)/T(m2y)
+//   V = (m2 D(m2x) - m1 D(m1x)) / (m2 G(m2x) - m1 D(m1x)) T(m2x)/T(m2y),
+// a_n and b_n take the homogeneous form with D(my)/m replaced by
+// (D(m2y) - U G(m2y)) / (m2 (1 - U)) and m D(my) by m2 (D(m2y) - V G(m2y)) /
+// (1 - V); U = V = 0 gives the homogeneous sphere back.  G and T follow the
+// upward recurrences G_n = 1/(n/z - G_{n-1}) - n/z and
+// T_n = T_{n-1} (n/z - D_{n-1}) / (n/z - G_{n-1}), from G_0 = T_0 = -tan z.
+struct Series {
+    double sext, ssca, sg;
+};
+
+__device__ Series mie_series(double lam, cd Nm, cd Ns, double r, bool coated, cd Nc, double rc, int nn_cap,
+                             cd* scratch, size_t stride, size_t dstride)
+{
+    const double pi = 3.141592653589793;
+    const double k0 = 2.0 * pi / lam;
+    const cd x_out = (k0 * r) * Nm;                 // host size parameter of the outer surface
+    const cd m2 = Ns / Nm;
+    const cd y2 = m2 * x_out;                       // shell (or particle) argument at r
+    double ay = k0 * r * sqrt(abs2(Ns));
+    if (coated) ay = fmax(ay, k0 * rc * sqrt(abs2(Nc)));
+    int nn = series_length(ay) + 1;                 // eq. (15) needs a_{nmax+1}
+    if (nn > nn_cap) nn = nn_cap;
+    const int nmax = nn - 1;
+    cd* D2y = scratch;                              // D_n(m2 y)
+    const cd D2y0 = log_derivative_strided(y2, nn, sqrt(abs2(y2)), D2y, stride);
+    cd* D1x = scratch + dstride;                    // D_n(m1 x)   (coated only)
+    cd* D2x = scratch + 2 * dstride;                // D_n(m2 x)
+    cd m1 = mk(0.0, 0.0), z1 = mk(0.0, 0.0), z2 = mk(0.0, 0.0);
+    cd G2x = mk(0.0, 0.0), G2y = mk(0.0, 0.0), T2x = mk(0.0, 0.0), T2y = mk(0.0, 0.0);
+    cd D2x0 = mk(0.0, 0.0);
+    if (coated) {
+        const cd x_in = (k0 * rc) * Nm;
+        m1 = Nc / Nm;
+        z1 = m1 * x_in;
+        z2 = m2 * x_in;
+        log_derivative_strided(z1, nn, sqrt(abs2(z1)), D1x, stride);
+        D2x0 = log_derivative_strided(z2, nn, sqrt(abs2(z2)), D2x, stride);
+        const cd t2x = csin_(z2) / ccos_(z2), t2y = csin_(y2) / ccos_(y2);
+        G2x = mk(-t2x.re, -t2x.im); T2x = G2x;      // G_0 = T_0 = -tan z
+        G2y = mk(-t2y.re, -t2y.im); T2y = G2y;
+    }
+    // upward psi_n(x), xi_n(x) = x h_n^(1)(x) of the outer host argument
+    const cd ix = recip(x_out);
+    const cd sx = csin_(x_out), cx = ccos_(x_out);
+    cd psi_m1 = cx, psi_0 = sx;
+    cd xi_m1 = mk(cx.re - sx.im, cx.im + sx.re);   // cos x + i sin x
+    cd xi_0 = mk(sx.re + cx.im, sx.im - cx.re);    // sin x - i cos x
+    const cd iNm2 = recip(Nm * Nm);
+    const cd im2 = recip(m2);
+    const cd iz2 = coated ? recip(z2) : mk(0.0, 0.0), iy2 = recip(y2);
+    cd D2x_prev = D2x0, D2y_prev = D2y0;
+    Series S{0.0, 0.0, 0.0};
+    cd a_prev = mk(0.0, 0.0), b_prev = mk(0.0, 0.0);
+    bool done = false;
+    for (int n = 1; n <= nn && !done; ++n) {
+        const double fn = (double)n;
+        const cd psi_n = (2.0 * fn - 1.0) * ix * psi_0 - psi_m1;
+        const cd xi_n = (2.0 * fn - 1.0) * ix * xi_0 - xi_m1;
+        cd an, bn;
+        const cd Dy = D2y[(size_t)n * stride];
+        cd ta = Dy * im2, tb = m2 * Dy;            // homogeneous: D(my)/m and m D(my)
+        if (coated) {
+            const cd nz2 = fn * iz2, ny2 = fn * iy2;
+            // upward G_n and T_n of the shell arguments
+            T2x = T2x * (nz2 - D2x_prev) / (nz2 - G2x);
+            T2y = T2y * (ny2 - D2y_prev) / (ny2 - G2y);
+            G2x = recip(nz2 - G2x) - nz2;
+            G2y = recip(ny2 - G2y) - ny2;
+            const cd D1 = D1x[(size_t)n * stride], D2 = D2x[(size_t)n * stride];
+            const cd ratio = T2x / T2y;
+            const cd U = (m2 * D1 - m1 * D2) / (m2 * D1 - m1 * G2x) * ratio;
+            const cd V = (m2 * D2 - m1 * D1) / (m2 * G2x - m1 * D1) * ratio;
+            const cd one = mk(1.0, 0.0);
+            ta = (Dy - U * G2y) / (m2 * (one - U));
+            tb = m2 * (Dy - V * G2y) / (one - V);
+            D2x_prev = D2;
+            D2y_prev = Dy;
+        }
+        if (!isfinite(xi_n.re) || !isfinite(xi_n.im) || abs2(xi_n) > 1e300) {
+            // psi_n/xi_n -> 0 far above |x|: remaining coefficients vanish
+            an = mk(0.0, 0.0); bn = mk(0.0, 0.0);
+            done = true;
+        } else {
+            const cd nx = fn * ix;
+            const cd ua = ta + nx, ub = tb + nx;
+            an = (ua * psi_n - psi_0) / (ua * xi_n - xi_0);
+            bn = (ub * psi_n - psi_0) / (ub * xi_n - xi_0);
+        }
+        if (n >= 2) {   // cross term of eq. (15) for the pair (n-1, n)
+            const double f1 = fn - 1.0;
+            S.sg += f1 * (f1 + 2.0) / (f1 + 1.0) * ((a_prev * conj_(an)).re + (b_prev * conj_(bn)).re);
+        }
+        if (n <= nmax) {
+            S.sext += (2.0 * fn + 1.0) * ((an + bn) * iNm2).re;
+            S.ssca += (2.0 * fn + 1.0) * (abs2(an) + abs2(bn));
+            S.sg += (2.0 * fn + 1.0) / (fn * (fn + 1.0)) * (an * conj_(bn)).re;
+        }
+        a_prev = an; b_prev = bn;
+        psi_m1 = psi_0; psi_0 = psi_n;
+        xi_m1 = xi_0; xi_0 = xi_n;
+    }
+    return S;
+}
+
+// One thread per size unit (entry, sub): Gaussian spreads give 101 units per
+// entry (unused units are skipped), everything else one.
+__global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
 {
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t nthreads = (size_t)gridDim.x * blockDim.x;
     const double pi = 3.141592653589793;
-    for (size_t j = tid; j < (size_t)a.n_entries; j += nthreads) {
+    const size_t n_units = (size_t)a.n_entries * a.units;
+    const size_t dstride = ((size_t)a.nn_cap + 1) * nthreads;
+    for (size_t u = tid; u < n_units; u += nthreads) {
+        const size_t j = u / a.units;
+        const int sub = (int)(u % a.units);
         const int c = a.cell_of[j];
-        const double lam = a.lam[c], r = a.r[j];
+        const double lam = a.lam[c];
+        const double sd = a.sd ? a.sd[j] : 0.0;
+        const double rc = a.r_core ? a.r_core[j] : 0.0;
+        double r = a.r[j];
+        if (sd > 0.0) {
+            const double d = spread_diameter(2.0 * r, sd, sub);
+            if (!(d > 0.0)) continue;                  // sizes that are not positive are left out
+            r = 0.5 * d;
+        } else if (sub > 0) {
+            continue;
+        }
         const cd Nm = mk(a.n_m[c], a.k_m[c]);
         const cd Np = mk(a.n_p[j], a.k_p[j]);
-        const double k0r = 2.0 * pi * r / lam;
-        const cd x = k0r * Nm;
-        const cd m = Np / Nm;
-        const cd y = m * x;
-        // |y| by the same expression as optics_scan, so the series length
-        // never exceeds the scratch the host sized from it
-        const double ay = 2.0 * pi * r * sqrt(a.n_p[j] * a.n_p[j] + a.k_p[j] * a.k_p[j]) / lam;
-        int nn = series_length(ay) + 1;              // eq. (15) needs a_{nmax+1}
-        if (nn > a.nn_cap) nn = a.nn_cap;
-        const int nmax = nn - 1;
-        // D_n(y), n = 1..nn, downward from far above; stored strided
-        cd* D = reinterpret_cast<cd*>(a.scratch) + tid;   // D[n * nthreads]
-        int nstart = nn;
-        if (ceil(ay) > nstart) nstart = (int)ceil(ay);
-        nstart += 16;
-        const cd iy = recip(y);
-        cd d = mk(0.0, 0.0);
-        for (int n = nstart; n > nn; --n) {
-            const cd ny = (double)n * iy;
-            d = ny - recip(d + ny);
-        }
-        D[(size_t)nn * nthreads] = d;
-        for (int n = nn; n >= 2; --n) {
-            const cd ny = (double)n * iy;
-            d = ny - recip(d + ny);
-            D[(size_t)(n - 1) * nthreads] = d;
-        }
-        // upward psi_n(x), xi_n(x) = x h_n^(1)(x)
-        const cd ix = recip(x);
-        const cd sx = csin_(x), cx = ccos_(x);
-        cd psi_m1 = cx, psi_0 = sx;
-        cd xi_m1 = mk(cx.re - sx.im, cx.im + sx.re);   // cos x + i sin x
-        cd xi_0 = mk(sx.re + cx.im, sx.im - cx.re);    // sin x - i cos x
-        const cd iNm2 = recip(Nm * Nm);
-        const cd im = recip(m);
-        double sext = 0.0, ssca = 0.0, sg = 0.0;
-        cd a_prev = mk(0.0, 0.0), b_prev = mk(0.0, 0.0);
-        bool done = false;
-        for (int n = 1; n <= nn && !done; ++n) {
-            const double fn = (double)n;
-            const cd psi_n = (2.0 * fn - 1.0) * ix * psi_0 - psi_m1;
-            const cd xi_n = (2.0 * fn - 1.0) * ix * xi_0 - xi_m1;
-            cd an, bn;
-            if (!isfinite(xi_n.re) || !isfinite(xi_n.im) || abs2(xi_n) > 1e300) {
-                // psi_n/xi_n -> 0 far above |x|: remaining coefficients vanish
-                an = mk(0.0, 0.0); bn = mk(0.0, 0.0);
-                done = true;
-            } else {
-                const cd Dn = D[(size_t)n * nthreads];
-                const cd nx = fn * ix;
-                const cd ta = Dn * im + nx;
-                const cd tb = m * Dn + nx;
-                an = (ta * psi_n - psi_0) / (ta * xi_n - xi_0);
-                bn = (tb * psi_n - psi_0) / (tb * xi_n - xi_0);
-            }
-            if (n >= 2) {   // cross term of eq. (15) for the pair (n-1, n)
-                const double f1 = fn - 1.0;
-                sg += f1 * (f1 + 2.0) / (f1 + 1.0) * ((a_prev * conj_(an)).re + (b_prev * conj_(bn)).re);
-            }
-            if (n <= nmax) {
-                sext += (2.0 * fn + 1.0) * ((an + bn) * iNm2).re;
-                ssca += (2.0 * fn + 1.0) * (abs2(an) + abs2(bn));
-                sg += (2.0 * fn + 1.0) / (fn * (fn + 1.0)) * (an * conj_(bn)).re;
-            }
-            a_prev = an; b_prev = bn;
-            psi_m1 = psi_0; psi_0 = psi_n;
-            xi_m1 = xi_0; xi_0 = xi_n;
-        }
-        // eqs. (10)-(12)
+        const bool coated = rc > 0.0;
+        const cd Nc = coated ? mk(a.n_core[j], a.k_core[j]) : mk(1.0, 0.0);
+        cd* scratch = reinterpret_cast<cd*>(a.scratch) + tid;
+        const Series S = mie_series(lam, Nm, Np, r, coated, Nc, rc, a.nn_cap, scratch, nthreads, dstride);
+        // eqs. (10)-(12), cross sections referred to the (outer) radius r
         const double alpha = 4.0 * pi * r * a.k_m[c] / lam;
         double gam;
         if (fabs(alpha) < 1e-3)
@@ -172,11 +282,11 @@ __global__ void mie_entries(OpticsArgs a)
         else
             gam = 2.0 * (1.0 + (alpha - 1.0) * exp(alpha)) / (alpha * alpha);
         const double area = pi * r * r;
-        const double cext = lam * lam / (2.0 * pi) * sext;
-        const double csca = lam * lam * exp(-alpha) / (2.0 * pi * gam * abs2(Nm)) * ssca;
-        a.mie[3 * j + 0] = cext / area;
-        a.mie[3 * j + 1] = csca / area;
-        a.mie[3 * j + 2] = ssca > 0.0 ? 2.0 * sg / ssca : 0.0;
+        const double cext = lam * lam / (2.0 * pi) * S.sext;
+        const double csca = lam * lam * exp(-alpha) / (2.0 * pi * gam * abs2(Nm)) * S.ssca;
+        a.mie[3 * u + 0] = cext / area;
+        a.mie[3 * u + 1] = csca / area;
+        a.mie[3 * u + 2] = S.ssca > 0.0 ? 2.0 * S.sg / S.ssca : 0.0;
     }
 }
 
@@ -187,13 +297,38 @@ __global__ void emt_cells(OpticsArgs a)
     const int64_t b = a.offsets[c], e = a.offsets[c + 1];
     double mus = 0.0, mua = 0.0, gs = 0.0, F = 0.0;
     for (int64_t j = b; j < e; ++j) {
-        const double qe = a.mie[3 * j], qs = a.mie[3 * j + 1], gi = a.mie[3 * j + 2];
-        const double f = a.f[j], r = a.r[j];
-        const double ws = 1.5 * qs * f / (2.0 * r);
-        mus += ws;
-        mua += 1.5 * (qe - qs) * f / (2.0 * r);
-        gs += ws * gi;
+        const double f = a.f[j];
+        const double sd = a.sd ? a.sd[j] : 0.0;
+        const double* q = a.mie + 3 * (size_t)j * a.units;
         F += f;
+        if (sd > 0.0) {
+            // Gaussian weights of the 101 diameters, renormalised over the positive ones
+            const double d0 = 2.0 * a.r[j];
+            double wsum = 0.0;
+            for (int k = 0; k < kSpreadSizes; ++k) {
+                const double d = spread_diameter(d0, sd, k);
+                if (!(d > 0.0)) continue;
+                const double z = (d - d0) / sd;
+                wsum += exp(-0.5 * z * z);
+            }
+            for (int k = 0; k < kSpreadSizes; ++k) {
+                const double d = spread_diameter(d0, sd, k);
+                if (!(d > 0.0)) continue;
+                const double z = (d - d0) / sd;
+                const double fk = f * (exp(-0.5 * z * z) / wsum), rk = 0.5 * d;
+                const double* qk = q + 3 * k;
+                const double ws = 1.5 * qk[1] * fk / (2.0 * rk);
+                mus += ws;
+                mua += 1.5 * (qk[0] - qk[1]) * fk / (2.0 * rk);
+                gs += ws * qk[2];
+            }
+        } else {
+            const double r = a.r[j];
+            const double ws = 1.5 * q[1] * f / (2.0 * r);
+            mus += ws;
+            mua += 1.5 * (q[0] - q[1]) * f / (2.0 * r);
+            gs += ws * q[2];
+        }
     }
     double g = mus > 0.0 ? gs / mus : 0.0;
     if (mus < 0.0) mus = 0.0;

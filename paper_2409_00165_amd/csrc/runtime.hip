@@ -471,6 +471,9 @@ static const char* optics_field_name(int code)
     case fos::kOptErrKp: return "k_p (must be finite and >= 0)";
     case fos::kOptErrRadius: return "r (must be finite and > 0)";
     case fos::kOptErrFraction: return "f (must be finite and >= 0)";
+    case fos::kOptErrSpread: return "sd (must be finite and >= 0)";
+    case fos::kOptErrCore: return "core (0 <= r_core <= r, n_core > 0, k_core >= 0, finite)";
+    case fos::kOptErrSpreadCore: return "sd with a core (coated spheres take no size spread)";
     default: return "unknown field";
     }
 }
@@ -502,19 +505,22 @@ fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, 
         return fail(c, FOS_E_INVALID_ARG, "a particle array pointer is NULL");
     if ((e = grow(c->cell_of, c->cell_of_bytes, (size_t)std::max<int64_t>(P, 1) * sizeof(int))) != hipSuccess)
         return hip_fail(c, e, "optics scratch");
-    if ((e = grow(c->mie, c->mie_bytes, (size_t)std::max<int64_t>(P, 1) * 3 * sizeof(double))) != hipSuccess)
-        return hip_fail(c, e, "optics scratch");
+
     fos::OpticsArgs a{};
     a.n_cells = p->n_cells;
     a.n_entries = P;
     a.lam = p->lam; a.n_m = p->n_m; a.k_m = p->k_m; a.offsets = p->offsets;
     a.n_p = p->n_p; a.k_p = p->k_p; a.r = p->r; a.f = p->f;
+    a.sd = p->sd; a.r_core = p->r_core; a.n_core = p->n_core; a.k_core = p->k_core;
+    if (a.r_core && (!a.n_core || !a.k_core)) return fail(c, FOS_E_INVALID_ARG, "r_core given without n_core, k_core");
+    a.flags = reinterpret_cast<unsigned int*>(c->err_dev + 2);
     a.cell_of = c->cell_of;
     a.mie = c->mie;
     a.nmax = c->nmax_dev;
     a.err = c->err_dev;
     a.out_mu_s = mu_s; a.out_mu_a = mu_a; a.out_g = g; a.out_f64 = out_f64;
     if ((e = fos::launch_fill_u64(c->err_dev, ~0ull, 1, st)) != hipSuccess ||
+        (e = fos::launch_fill_u64(c->err_dev + 2, 0ull, 1, st)) != hipSuccess ||
         (e = fos::launch_fill_u64(reinterpret_cast<unsigned long long*>(c->nmax_dev), 0ull, 1, st)) != hipSuccess ||
         (e = fos::launch_optics_scan(a, st)) != hipSuccess)
         return hip_fail(c, e, "optics scan");
@@ -522,8 +528,13 @@ fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, 
             hipSuccess ||
         (e = hipMemcpyAsync(&c->aux_host[2], c->nmax_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&c->aux_host[1], c->err_dev + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(c, e, "optics verdict");
+    const unsigned int oflags = (unsigned int)(c->aux_host[1] & 0xFFFFFFFFull);
+    a.units = (oflags & fos::kOptHasSpread) ? fos::kSpreadSizes : 1;
+    a.d_arrays = (oflags & fos::kOptHasCore) ? 3 : 1;
     const unsigned long long w = *c->err_host;
     if (w != ~0ull) {
         char buf[256];
@@ -532,14 +543,18 @@ fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, 
     }
     const int nn_cap = (int)(c->aux_host[2] & 0xFFFFFFFFull);
     if (nn_cap > (1 << 20)) return fail(c, FOS_E_UNSUPPORTED, "Mie series longer than 2^20 terms");
+    if ((e = grow(c->mie, c->mie_bytes, (size_t)std::max<int64_t>(P, 1) * a.units * 3 * sizeof(double))) !=
+        hipSuccess)
+        return hip_fail(c, e, "optics scratch");
+    a.mie = c->mie;
     const int block = 256;
     int grid = c->n_cu * 4;
-    const int64_t need = (P + block - 1) / block;
+    const int64_t need = (P * a.units + block - 1) / block;
     if (need < grid) grid = (int)std::max<int64_t>(need, 1);
     a.nn_cap = std::max(nn_cap, 1);
     const size_t nthreads = (size_t)grid * block;
-    if ((e = grow(c->mie_scratch, c->mie_scratch_bytes, ((size_t)a.nn_cap + 1) * nthreads * sizeof(double2))) !=
-        hipSuccess)
+    if ((e = grow(c->mie_scratch, c->mie_scratch_bytes,
+                  (size_t)a.d_arrays * ((size_t)a.nn_cap + 1) * nthreads * sizeof(double2))) != hipSuccess)
         return hip_fail(c, e, "Mie scratch");
     a.scratch = c->mie_scratch;
     if ((e = fos::launch_mie(a, grid, block, st)) != hipSuccess) return hip_fail(c, e, "Mie kernel");

@@ -43,7 +43,8 @@ class fos_mc_problem(Structure):
 class fos_optics_problem(Structure):
     _fields_ = [("n_cells", c_int32), ("lam", c_void_p), ("n_m", c_void_p), ("k_m", c_void_p),
                 ("offsets", c_void_p), ("n_p", c_void_p), ("k_p", c_void_p), ("r", c_void_p),
-                ("f", c_void_p)]
+                ("f", c_void_p), ("sd", c_void_p), ("r_core", c_void_p), ("n_core", c_void_p),
+                ("k_core", c_void_p)]
 
 
 class fos_lognormal_problem(Structure):
@@ -343,9 +344,10 @@ def fos_mc_set_launch(ctx, launch) -> None:
 class OpticsProblem:
     """Device tensors of one fos_optics_problem (float64 cells, CSR particles)."""
 
-    def __init__(self, lam, n_m, k_m, offsets, n_p, k_p, r, f):
+    def __init__(self, lam, n_m, k_m, offsets, n_p, k_p, r, f, sd=None, r_core=None, n_core=None, k_core=None):
         import torch
-        self.tensors = dict(lam=lam, n_m=n_m, k_m=k_m, offsets=offsets, n_p=n_p, k_p=k_p, r=r, f=f)
+        self.tensors = dict(lam=lam, n_m=n_m, k_m=k_m, offsets=offsets, n_p=n_p, k_p=k_p, r=r, f=f, sd=sd,
+                            r_core=r_core, n_core=n_core, k_core=k_core)
         C = lam.numel()
         P = n_p.numel()
         s = fos_optics_problem()
@@ -353,17 +355,21 @@ class OpticsProblem:
         for k in ("lam", "n_m", "k_m"):
             setattr(s, k, _ptr(self.tensors[k], torch.float64, C))
         s.offsets = _ptr(offsets, torch.int64, C + 1)
-        for k in ("n_p", "k_p", "r", "f"):
-            setattr(s, k, _ptr(self.tensors[k], torch.float64, P) if P else None)
+        for k in ("n_p", "k_p", "r", "f", "sd", "r_core", "n_core", "k_core"):
+            t = self.tensors[k]
+            setattr(s, k, _ptr(t, torch.float64, P) if (P and t is not None) else None)
         self.n_cells, self.n_entries, self.struct = C, P, s
 
     @classmethod
     def from_request(cls, req, device="cuda"):
-        """From a workloads.optics_request() dict of numpy arrays."""
+        """From a workloads.optics_request() dict of numpy arrays (sd, r_core,
+        n_core, k_core optional)."""
         import numpy as np
         import torch
-        t = lambda k, dt=np.float64: torch.from_numpy(np.ascontiguousarray(req[k], dtype=dt)).to(device)
-        return cls(t("lam"), t("n_m"), t("k_m"), t("offsets", np.int64), t("n_p"), t("k_p"), t("r"), t("f"))
+        t = lambda k, dt=np.float64: (None if req.get(k) is None else
+                                      torch.from_numpy(np.ascontiguousarray(req[k], dtype=dt)).to(device))
+        return cls(t("lam"), t("n_m"), t("k_m"), t("offsets", np.int64), t("n_p"), t("k_p"), t("r"), t("f"),
+                   t("sd"), t("r_core"), t("n_core"), t("k_core"))
 
 
 class LognormalProblem:

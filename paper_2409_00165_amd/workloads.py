@@ -28,7 +28,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 
@@ -68,7 +68,13 @@ def species_b_index(lam: np.ndarray):
     return np.full_like(lam, 1.45), 0.5 * hw**2 / ((lam - 9.0) ** 2 + hw**2)
 
 
-SPECIES = {"A": species_a_index, "B": species_b_index}
+def air_index(lam: np.ndarray):
+    """Air (or vacuum): n = 1, k = 0 -- the core of a hollow particle."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return np.ones_like(lam), np.zeros_like(lam)
+
+
+SPECIES = {"A": species_a_index, "B": species_b_index, "air": air_index}
 
 
 def lognormal_bins(r_med: float, sigma_ln: float, n_bins: int = 20, span: float = 3.0):
@@ -101,8 +107,11 @@ class Particles:
     wavelength grid, a list of radii and their volume fractions."""
 
     species: str
-    radii: np.ndarray        # [n_sizes] um
+    radii: np.ndarray        # [n_sizes] um (outer radii of coated spheres)
     fractions: np.ndarray    # [n_sizes] volume fractions (sum = population f)
+    sd: Optional[np.ndarray] = None          # [n_sizes] standard deviation of the diameter (um), or None
+    core_species: Optional[str] = None       # coated spheres: core material ...
+    core_radii: Optional[np.ndarray] = None  # ... and core radii [n_sizes] (um)
 
 
 @dataclass
@@ -186,6 +195,28 @@ def paper_context_451(photons: int = 50_000) -> Workload:
     pop = Particles("A", np.array([0.2]), np.array([0.60]))
     d = Design([Layer(200.0, 1.5, 0.0, [pop])], photons=photons)
     return Workload("paper_context_451", lam, [d])
+
+
+def hollow_silica_50(shell_um: float = 0.1, photons: int = 100_000, n_lambda: int = 100) -> Workload:
+    """Shaped like the paper's core-shell example (Results, hollow particles):
+    a 50 um layer of 60 % hollow silica-like particles (core air, diameter
+    0.5 um; shell species B of thickness `shell_um`) in air, 100 wavelengths
+    log-spaced 0.3..16 um."""
+    lam = grid_log(0.3, 16.0, n_lambda)
+    rc = 0.25
+    pop = Particles("B", np.array([rc + shell_um]), np.array([0.60]), core_species="air", core_radii=np.array([rc]))
+    d = Design([Layer(50.0, 1.0, 0.0, [pop])], photons=photons)
+    return Workload("hollow_silica_50", lam, [d])
+
+
+def gaussian_spread_slab(sd_um: float = 0.1, photons: int = 100_000, n_lambda: int = 100) -> Workload:
+    """A 200 um film of species A (mean diameter 0.4 um, diameter standard
+    deviation `sd_um`, the paper's 101-size spread) at f = 0.2 in n_m = 1.5,
+    100 wavelengths log-spaced 0.3..16 um."""
+    lam = grid_log(0.3, 16.0, n_lambda)
+    pop = Particles("A", np.array([0.2]), np.array([0.2]), sd=np.array([sd_um]))
+    d = Design([Layer(200.0, 1.5, 1e-4, [pop])], photons=photons)
+    return Workload("gaussian_spread_slab", lam, [d])
 
 
 def stacks_3layer(n_designs: int = 4096, n_lambda: int = 100, seed: int = 20240900,
@@ -354,6 +385,9 @@ def optics_request(wl: Workload):
     counts = np.zeros(C, np.int64)
     # per (design, layer): species index arrays over lambda
     chunks_np, chunks_kp, chunks_r, chunks_f = [], [], [], []
+    chunks_x = []   # per (design, layer): (sd [per], r_core [per], n_core [nl, per], k_core [nl, per])
+    extra = any(p.sd is not None or p.core_species is not None for d in wl.designs for l in d.layers
+                for p in l.particles)
     for d, des in enumerate(wl.designs):
         for l in range(L):
             lay = des.layers[l] if l < len(des.layers) else None
@@ -367,25 +401,38 @@ def optics_request(wl: Workload):
             counts[cells] = per
             npl = np.zeros((nl, per)); kpl = np.zeros((nl, per))
             rl = np.zeros(per); fl = np.zeros(per)
+            sdl = np.zeros(per); rcl = np.zeros(per); ncl = np.ones((nl, per)); kcl = np.zeros((nl, per))
             j = 0
             for pop in lay.particles:
                 n, k = SPECIES[pop.species](lamv)
                 m = len(pop.radii)
                 npl[:, j:j + m] = n[:, None]; kpl[:, j:j + m] = k[:, None]
                 rl[j:j + m] = pop.radii; fl[j:j + m] = pop.fractions
+                if pop.sd is not None:
+                    sdl[j:j + m] = pop.sd
+                if pop.core_species is not None:
+                    nc, kc = SPECIES[pop.core_species](lamv)
+                    rcl[j:j + m] = pop.core_radii
+                    ncl[:, j:j + m] = nc[:, None]; kcl[:, j:j + m] = kc[:, None]
                 j += m
             chunks_np.append((cells, npl)); chunks_kp.append(kpl)
+            chunks_x.append((sdl, rcl, ncl, kcl))
             chunks_r.append(np.broadcast_to(rl, (nl, per))); chunks_f.append(np.broadcast_to(fl, (nl, per)))
     offsets = np.zeros(C + 1, np.int64)
     np.cumsum(counts, out=offsets[1:])
     P = int(offsets[-1])
     n_p = np.zeros(P); k_p = np.zeros(P); r = np.zeros(P); f = np.zeros(P)
-    for (cells, npl), kpl, rl, fl in zip(chunks_np, chunks_kp, chunks_r, chunks_f):
+    sd = np.zeros(P); r_core = np.zeros(P); n_core = np.ones(P); k_core = np.zeros(P)
+    for (cells, npl), kpl, rl, fl, (sdl, rcl, ncl, kcl) in zip(chunks_np, chunks_kp, chunks_r, chunks_f, chunks_x):
         per = npl.shape[1]
         idx = offsets[cells][:, None] + np.arange(per)[None, :]
         n_p[idx] = npl; k_p[idx] = kpl; r[idx] = rl; f[idx] = fl
-    return {"lam": lam, "n_m": n_m, "k_m": k_m, "offsets": offsets,
-            "n_p": n_p, "k_p": k_p, "r": r, "f": f, "cells": C, "max_layers": L}
+        sd[idx] = sdl; r_core[idx] = rcl; n_core[idx] = ncl; k_core[idx] = kcl
+    out = {"lam": lam, "n_m": n_m, "k_m": k_m, "offsets": offsets,
+           "n_p": n_p, "k_p": k_p, "r": r, "f": f, "cells": C, "max_layers": L}
+    if extra:
+        out.update({"sd": sd, "r_core": r_core, "n_core": n_core, "k_core": k_core})
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -163,9 +163,11 @@ __global__ __launch_bounds__(1024) void chunk_scan(const float4* table, int rf, 
 // current layer in registers and re-reads the LDS slot only when it launches
 // a photon or crosses into another layer.  Lanes that finish are refilled
 // once at least refill_min of them are idle, so a wave keeps walking while
-// the photons of an old chunk drain.  Outcomes are counted per slot in LDS
-// (a ballot/popcount per outcome when all finishing lanes share a slot) and
-// added to the item's uint64 tallies when a slot is recycled and at exit.
+// the photons of an old chunk drain.  Outcomes and steps are counted per
+// slot in LDS (one LDS add per finishing lane) and added to the item's
+// uint64 tallies when a slot is recycled and at exit.  The refill check runs
+// after every step that ends a photon and at least every kStepsPerCheck
+// steps.
 constexpr int kSlots = 4;
 
 struct LaneLayer {
@@ -350,85 +352,81 @@ __global__ void walk(WalkArgs a)
 
         // ---------------- walk ----------------
         for (int it = 0; it < kStepsPerCheck; ++it) {
-            int term = -1;
-            if (alive) {
+            const bool go = alive && k < max_steps;
+            int term = (alive && !go) ? (int)kCap : -1;        // step budget used up
+            if (go) {
                 ++k;
-                if (k > max_steps) {
-                    k = max_steps;
-                    term = kCap;
+                const uint4 x = philox4x32_10(p_lo, p_hi, k, item, k0, k1);
+                const float U1 = u24(x.y);
+                if (s == 0.f) s = neg_ln(1.0f - u24(x.x));
+                const float aa = fabsf(uz);
+                bool interact;
+                if (aa == 0.f) {
+                    interact = P.mut > 0.f;
+                    if (!interact) term = kCap;      // parallel in a clear layer
                 } else {
-                    const uint4 x = philox4x32_10(p_lo, p_hi, k, item, k0, k1);
-                    const float U1 = u24(x.y);
-                    if (s == 0.f) s = neg_ln(1.0f - u24(x.x));
-                    const float aa = fabsf(uz);
-                    bool interact;
-                    if (aa == 0.f) {
-                        interact = P.mut > 0.f;
-                        if (!interact) term = kCap;      // parallel in a clear layer
-                    } else {
-                        const bool down = uz > 0.f;
-                        const float dz = down ? P.thick - z : z;
-                        interact = !(P.mut * dz <= s * aa);
-                        if (!interact) {
-                            // reach the interface
-                            s = fmaxf(s - P.mut * dz * fast_rcp(aa), 0.f);
-                            z = down ? P.thick : 0.f;
-                            const uint32_t fl = P.flags;
-                            const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);
-                            const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);
-                            float R = 0.f, ct = aa;
-                            if (down && (fl & kComplexDn)) {
-                                const float4 h0 = tab[slot * rf];
-                                R = fresnel_complex(aa, P.n, h0.z, h0.w);
-                            } else if (!matched) {
-                                const float m = down ? P.m_dn : P.m_up;
-                                const float s2t = m * m * (1.f - aa * aa);
-                                if (s2t >= 1.f) {
-                                    R = 1.f;
-                                } else {
-                                    ct = fast_sqrt(1.f - s2t);
-                                    R = fresnel_real(aa, ct, m);
-                                }
-                            }
-                            if (U1 < R) {
-                                uz = -uz;
-                            } else if (ex) {
-                                term = down ? kTrans : kRDiff;
+                    const bool down = uz > 0.f;
+                    const float dz = down ? P.thick - z : z;
+                    interact = !(P.mut * dz <= s * aa);
+                    if (!interact) {
+                        // reach the interface
+                        s = fmaxf(s - P.mut * dz * fast_rcp(aa), 0.f);
+                        z = down ? P.thick : 0.f;
+                        const uint32_t fl = P.flags;
+                        const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);
+                        const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);
+                        float R = 0.f, ct = aa;
+                        if (down && (fl & kComplexDn)) {
+                            const float4 h0 = tab[slot * rf];
+                            R = fresnel_complex(aa, P.n, h0.z, h0.w);
+                        } else if (!matched) {
+                            const float m = down ? P.m_dn : P.m_up;
+                            const float s2t = m * m * (1.f - aa * aa);
+                            if (s2t >= 1.f) {
+                                R = 1.f;
                             } else {
-                                layer += down ? 1 : -1;
-                                load_layer(tab + slot * rf, layer, P);
-                                uz = down ? ct : -ct;
-                                z = down ? 0.f : P.thick;
+                                ct = fast_sqrt(1.f - s2t);
+                                R = fresnel_real(aa, ct, m);
                             }
-                        } else {
-                            z = fmaf(uz * s, P.inv_mut, z);
-                            s = 0.f;
                         }
+                        if (U1 < R) {
+                            uz = -uz;
+                        } else if (ex) {
+                            term = down ? kTrans : kRDiff;
+                        } else {
+                            layer += down ? 1 : -1;
+                            load_layer(tab + slot * rf, layer, P);
+                            uz = down ? ct : -ct;
+                            z = down ? 0.f : P.thick;
+                        }
+                    } else {
+                        z = fmaf(uz * s, P.inv_mut, z);
+                        s = 0.f;
                     }
-                    if (interact) {
-                        bool scatter;
+                }
+                if (interact) {
+                    bool scatter;
+                    if constexpr (WEIGHTED) {
+                        // deposit mu_a/mu_t of the weight, scatter the rest
+                        const float wn = wgt * P.alb;
+                        absd += wgt - wn;
+                        wgt = wn;
+                        scatter = wgt > 0.f;
+                        if (!scatter) term = kAbs;
+                    } else {
+                        scatter = U1 < P.alb;
+                        if (!scatter) term = kAbs;
+                    }
+                    if (scatter) {
+                        const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,
+                                               u24(x.z));
+                        const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
+                        const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
+                        uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);
                         if constexpr (WEIGHTED) {
-                            // deposit mu_a/mu_t of the weight, scatter the rest
-                            const float wn = wgt * P.alb;
-                            absd += wgt - wn;
-                            wgt = wn;
-                            scatter = wgt > 0.f;
-                            if (!scatter) term = kAbs;
-                        } else {
-                            scatter = U1 < P.alb;
-                            if (!scatter) term = kAbs;
-                        }
-                        if (scatter) {
-                            const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,
-                                                   u24(x.z));
-                            const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
-                            const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
-                            uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);
-                            if constexpr (WEIGHTED) {
-                                if (wgt < kRouletteThreshold) {
-                                    if (U1 < kRouletteChance) wgt = wgt / kRouletteChance;
-                                    else term = kWRoulette;
-                                }
+                            if (wgt < kRouletteThreshold) {
+                                if (U1 < kRouletteChance) wgt = wgt / kRouletteChance;
+                                else term = kWRoulette;
                             }
                         }
                     }
@@ -459,22 +457,14 @@ __global__ void walk(WalkArgs a)
                         }
                     }
                 } else {
+                    // one LDS add per finishing lane and counter: about one
+                    // photon ends per wave-step, and per-outcome ballots cost
+                    // more scalar and vector issue than the adds they save
                     if (term >= 0) {
                         alive = false;
-                        atomicAdd(cnt + slot * NT + kSteps, (unsigned long long)k);
-                    }
-                    const int lead = __builtin_ctzll(tm);
-                    const int s0 = __shfl(slot, lead);
-                    if (ballot64(term >= 0 && slot != s0) == 0ull) {
-                        // every finishing lane shares slot s0: one popcount per outcome
-                        unsigned long long* c0 = cnt + s0 * NT;
-#pragma unroll
-                        for (int o = kRDiff; o <= kCap; ++o) {
-                            const uint64_t bo = ballot64(term == o);
-                            if (bo != 0ull && lane == 0) atomicAdd(c0 + o, (unsigned long long)__popcll(bo));
-                        }
-                    } else if (term >= 0) {
-                        atomicAdd(cnt + slot * NT + term, 1ull);
+                        unsigned long long* c0 = cnt + slot * NT;
+                        atomicAdd(c0 + kSteps, (unsigned long long)k);
+                        atomicAdd(c0 + term, 1ull);
                     }
                 }
                 if (__popcll(ballot64(!alive)) >= a.refill_min) break;
@@ -505,9 +495,9 @@ hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, b
 {
     const size_t lds = walk_lds_bytes(block, a.max_layers, weighted);
     if (weighted)
-        hipLaunchKernelGGL((walk<4, true>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((walk<16, true>), dim3(grid), dim3(block), lds, st, a);
     else
-        hipLaunchKernelGGL((walk<4, false>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((walk<16, false>), dim3(grid), dim3(block), lds, st, a);
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     c->n_cu = prop.multiProcessorCount;
     c->defaults.block_size = 256;
     c->defaults.refill_min = 8;
-    c->defaults.chunk = 4096;
+    c->defaults.chunk = 2048;
     c->defaults.blocks_per_cu = 8;
     c->defaults.max_steps = 100000000ull;
     DeviceGuard g(hip_device);

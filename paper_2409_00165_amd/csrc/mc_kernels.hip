@@ -211,7 +211,10 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
 // draws; the packet deposits mu_a/mu_t of its weight at each interaction,
 // always scatters, plays roulette below kRouletteThreshold, and tallies
 // weights (kNTallyW counters) instead of photon counts (kNTally).
-template <int kStepsPerCheck, bool WEIGHTED>
+// SINGLE is for problems whose items all have one layer: a photon that is
+// not reflected at a face always leaves, so the layer-change code is not
+// compiled in.
+template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE>
 __global__ void walk(WalkArgs a)
 {
     constexpr int NT = WEIGHTED ? kNTallyW : kNTally;
@@ -391,7 +394,7 @@ __global__ void walk(WalkArgs a)
                         }
                         if (U1 < R) {
                             uz = -uz;
-                        } else if (ex) {
+                        } else if (SINGLE || ex) {
                             term = down ? kTrans : kRDiff;
                         } else {
                             layer += down ? 1 : -1;
@@ -494,10 +497,15 @@ size_t walk_lds_bytes(int block_size, int max_layers, bool weighted)
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted)
 {
     const size_t lds = walk_lds_bytes(block, a.max_layers, weighted);
-    if (weighted)
-        hipLaunchKernelGGL((walk<16, true>), dim3(grid), dim3(block), lds, st, a);
+    const bool single = a.max_layers == 1;
+    if (weighted && single)
+        hipLaunchKernelGGL((walk<16, true, true>), dim3(grid), dim3(block), lds, st, a);
+    else if (weighted)
+        hipLaunchKernelGGL((walk<16, true, false>), dim3(grid), dim3(block), lds, st, a);
+    else if (single)
+        hipLaunchKernelGGL((walk<16, false, true>), dim3(grid), dim3(block), lds, st, a);
     else
-        hipLaunchKernelGGL((walk<16, false>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((walk<16, false, false>), dim3(grid), dim3(block), lds, st, a);
     return hipGetLastError();
 }
 

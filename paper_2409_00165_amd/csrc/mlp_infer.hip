@@ -17,7 +17,8 @@
 // A operand, streamed from L2 in a pre-swizzled fragment order (one coalesced
 // 1 KB load per 16 x 32 fragment), and the activations are the B operand read
 // from LDS.  A lane's accumulator then holds 4 consecutive neurons of one
-// row, so the bias + GELU epilogue writes 8-byte bf16 quads back to LDS.
+// row: the biases enter as the first product's accumulator, and the GELU
+// epilogue writes 8-byte bf16 quads back to LDS.
 //
 // Work split inside a workgroup (4 waves, TILE = kInferTile rows): wave w
 // owns neurons 64w .. 64w+63 of every hidden layer for all rows (TILE/4
@@ -58,22 +59,33 @@ __device__ __forceinline__ floatx4 mfma(const bf16x8& a, const bf16x8& b, const 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// bias + GELU of a wave's 64 neurons x TILE rows, written to H as bf16 quads
-template <int TILE>
-__device__ __forceinline__ void epilogue(floatx4 (&acc)[4][TILE / 16], const float* __restrict__ bias, __bf16* H,
-                                         int w, int q, int c16)
+// The 4 biases of the neurons a lane's accumulator quad holds in tile j: the
+// first product of a layer starts from them instead of from zero, so the
+// epilogue has no bias add.
+__device__ __forceinline__ void bias_quads(floatx4 (&b)[4], const float* __restrict__ bias, int w, int q)
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int n0 = 16 * (4 * w + j) + 4 * q;
-        const float b0 = bias[n0], b1 = bias[n0 + 1], b2 = bias[n0 + 2], b3 = bias[n0 + 3];
+        b[j] = {bias[n0], bias[n0 + 1], bias[n0 + 2], bias[n0 + 3]};
+    }
+}
+
+// GELU of a wave's 64 neurons x TILE rows (biases already in the
+// accumulators), written to H as bf16 quads
+template <int TILE>
+__device__ __forceinline__ void epilogue(floatx4 (&acc)[4][TILE / 16], __bf16* H, int w, int q, int c16)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n0 = 16 * (4 * w + j) + 4 * q;
 #pragma unroll
         for (int i = 0; i < TILE / 16; ++i) {
             bf16x4 v;
-            v[0] = (__bf16)gelu_sig(acc[j][i][0] + b0);
-            v[1] = (__bf16)gelu_sig(acc[j][i][1] + b1);
-            v[2] = (__bf16)gelu_sig(acc[j][i][2] + b2);
-            v[3] = (__bf16)gelu_sig(acc[j][i][3] + b3);
+            v[0] = (__bf16)gelu_sig(acc[j][i][0]);
+            v[1] = (__bf16)gelu_sig(acc[j][i][1]);
+            v[2] = (__bf16)gelu_sig(acc[j][i][2]);
+            v[3] = (__bf16)gelu_sig(acc[j][i][3]);
             *reinterpret_cast<bf16x4*>(H + (16 * i + c16) * kHRow + n0) = v;
         }
     }
@@ -165,17 +177,19 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
         __syncthreads();   // X written / previous member's output layer done with H
         {
             bf16x8 wf[4];
+            floatx4 b[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 wf[j] = *reinterpret_cast<const bf16x8*>(P + kPkOffL1 + ((size_t)(4 * w + j) * 64 + lane) * 8);
+            bias_quads(b, F + kOffB1, w, q);
 #pragma unroll
             for (int i = 0; i < kTile / 16; ++i) {
                 const bf16x8 xf = *reinterpret_cast<const bf16x8*>(X + (16 * i + c16) * kXRow + 8 * q);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wf[j], xf, zero4);
+                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wf[j], xf, b[j]);
             }
         }
-        epilogue<TILE>(acc, F + kOffB1, H, w, q, c16);
+        epilogue<TILE>(acc, H, w, q, c16);
 
         // hidden layers 2..4, in place in H.  The weight fragments of k-step
         // s + 1 are in flight while k-step s multiplies (two register sets
@@ -198,15 +212,17 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
                 }
             };
             bf16x8 wa[4], wb[4];
+            floatx4 b[4];
             load(wa, 0);
             load(wb, 1);
+            bias_quads(b, F + boff, w, q);
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();   // H of the previous layer complete
 #pragma unroll
             for (int i = 0; i < kTile / 16; ++i) {
                 const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + (16 * i + c16) * kHRow + 8 * q);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wa[j], hf, zero4);
+                for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wa[j], hf, b[j]);
             }
             // the scheduling barriers keep each prefetch ahead of the products
             // it overlaps (left alone, the scheduler sinks the loads past them)
@@ -223,7 +239,7 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
             }
             step(wb, 7);
             __syncthreads();   // every wave done reading this layer's input
-            epilogue<TILE>(acc, F + boff, H, w, q, c16);
+            epilogue<TILE>(acc, H, w, q, c16);
         }
 
         // output layer: wave w takes the OT row tiles OT w .. OT w + OT - 1

@@ -323,6 +323,34 @@ def test_bit_identical_across_launch_configs(ctx, torch):
     assert not (run_gpu(ctx, a, 1235) == ref).all()
 
 
+def test_single_layer_build_matches_general_build(ctx, torch):
+    """Problems whose items all have one layer run a build of the walk without
+    the layer-change code.  The same items padded to three layer slots (still
+    one layer each) run the general build; both forms of the walk must give
+    the same tallies bit for bit."""
+    from paper_2409_00165_amd import fos
+    from gpu_helpers import device_problem
+    rng = np.random.default_rng(12)
+    I = 24
+    cols = [rng.uniform(0.05, 20, I), rng.uniform(1e-3, 0.5, I), rng.uniform(-0.5, 0.95, I),
+            rng.uniform(1.0, 1.8, I), rng.uniform(1.0, 30.0, I)]
+    kw = dict(n_lower=np.where(rng.uniform(size=I) < 0.5, 1.0, 3.5),
+              k_lower=np.where(rng.uniform(size=I) < 0.5, 0.0, 0.02), mu0=rng.uniform(0.3, 1.0, I),
+              photons=rng.integers(1000, 20000, I))
+    one = make_arrays(*[c[:, None] for c in cols], **kw)
+    three = make_arrays(*[np.repeat(c[:, None], 3, axis=1) for c in cols], n_layers=1, **kw)
+    assert one["mu_s"].shape[1] == 1 and three["mu_s"].shape[1] == 3
+    assert np.array_equal(run_gpu(ctx, one, 77), run_gpu(ctx, three, 77))
+    w = []
+    for a in (one, three):
+        prob = device_problem(a)
+        tal = torch.zeros(I * fos.N_TALLY_W, dtype=torch.int64, device="cuda")
+        fos.fos_mc_run_weighted(ctx, prob, 78, tal)
+        torch.cuda.synchronize()
+        w.append(tal.cpu().numpy())
+    assert np.array_equal(w[0], w[1])
+
+
 def test_graph_capture_replays_match_eager(ctx, torch):
     from paper_2409_00165_amd import fos
     from gpu_helpers import device_problem

@@ -18,7 +18,8 @@
 // 1 KB load per 16 x 32 fragment), and the activations are the B operand read
 // from LDS.  A lane's accumulator then holds 4 consecutive neurons of one
 // row: the biases enter as the first product's accumulator, and the GELU
-// epilogue writes 8-byte bf16 quads back to LDS.
+// epilogue writes two such quads (one per 16-neuron tile) as one 16-byte
+// chunk back to LDS (layout below).
 //
 // Work split inside a workgroup (4 waves, TILE = kInferTile rows): wave w
 // owns neurons 64w .. 64w+63 of every hidden layer for all rows (TILE/4
@@ -39,7 +40,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kHRow = kHidden + 8;           // bf16 per LDS activation row (528 B: conflict-free b128 reads)
+constexpr int kHRow = kHidden;               // bf16 per LDS activation row (512 B, 16-byte chunks swizzled)
 constexpr int kXRow = 32 + 8;                // bf16 per LDS input-fragment row
 
 // gelu(z) = 0.5 z (1 + tanh(u)), u = sqrt(2/pi)(z + 0.044715 z^3), evaluated
@@ -71,22 +72,42 @@ __device__ __forceinline__ void bias_quads(floatx4 (&b)[4], const float* __restr
     }
 }
 
+// Activations in LDS.  Hidden neuron n = 32b + 16t + 4q + e (b = 32-column
+// block, t = which of the block's two 16-neuron tiles, q = lane quarter,
+// e = 0..3) sits in column 32b + 8q + 4t + e, so the two 4-neuron quads a
+// lane holds for the tiles of one block are 16 contiguous bytes (the next
+// layer's weights are packed with the same K order).  Row r keeps its
+// 16-byte chunks in XOR order: logical chunk c is stored at c ^ (r & 15).
+// With the LDS serving 16 consecutive lanes per pass, the 16-byte reads of
+// the B operand (16 rows, one chunk) and the 16-byte writes of the epilogue
+// (16 rows, one chunk) both hit 16 distinct bank groups.
+__device__ __forceinline__ int h_chunk(int row, int chunk) { return (chunk ^ (row & 15)) * 8; }
+
+// logical neuron index of physical activation column p
+__host__ __device__ __forceinline__ int h_neuron(int p)
+{
+    return (p & ~31) + (((p >> 2) & 1) << 4) + (((p >> 3) & 3) << 2) + (p & 3);
+}
+
 // GELU of a wave's 64 neurons x TILE rows (biases already in the
-// accumulators), written to H as bf16 quads
+// accumulators), written to H as 16-byte chunks (tiles 2m and 2m + 1 of a
+// wave form block 2w + m)
 template <int TILE>
 __device__ __forceinline__ void epilogue(floatx4 (&acc)[4][TILE / 16], __bf16* H, int w, int q, int c16)
 {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n0 = 16 * (4 * w + j) + 4 * q;
+    for (int m = 0; m < 2; ++m) {
+        const int chunk = 4 * (2 * w + m) + q;
 #pragma unroll
         for (int i = 0; i < TILE / 16; ++i) {
-            bf16x4 v;
-            v[0] = (__bf16)gelu_sig(acc[j][i][0]);
-            v[1] = (__bf16)gelu_sig(acc[j][i][1]);
-            v[2] = (__bf16)gelu_sig(acc[j][i][2]);
-            v[3] = (__bf16)gelu_sig(acc[j][i][3]);
-            *reinterpret_cast<bf16x4*>(H + (16 * i + c16) * kHRow + n0) = v;
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = (__bf16)gelu_sig(acc[2 * m][i][e]);
+                v[4 + e] = (__bf16)gelu_sig(acc[2 * m + 1][i][e]);
+            }
+            const int r = 16 * i + c16;
+            *reinterpret_cast<bf16x8*>(H + r * kHRow + h_chunk(r, chunk)) = v;
         }
     }
 }
@@ -117,13 +138,13 @@ __global__ void pack_infer_kernel(const float* __restrict__ params, __bf16* __re
         const size_t r = (e - kPkOffL2) % kPkHid;
         const int layer = (int)((e - kPkOffL2) / kPkHid);
         const int t = (int)(r / 4096), s = (int)(r / 512) % 8, l = (int)(r / 8) % 64, j = (int)(r % 8);
-        const int n = 16 * t + l % 16, k = 32 * s + 8 * (l / 16) + j;
+        const int n = 16 * t + l % 16, k = h_neuron(32 * s + 8 * (l / 16) + j);
         const size_t off = layer == 0 ? kOffW2 : layer == 1 ? kOffW3 : kOffW4;
         v = P[off + (size_t)k * kHidden + n];
     } else {
         const size_t r = e - kPkOffOut;
         const int s = (int)(r / 512), l = (int)(r / 8) % 64, j = (int)(r % 8);
-        const int n = l % 16, k = 32 * s + 8 * (l / 16) + j;
+        const int n = l % 16, k = h_neuron(32 * s + 8 * (l / 16) + j);
         v = n < 3 ? P[kOffW5 + k * 3 + n] : 0.0f;
     }
     pk[(size_t)m * kPkParams + e] = (__bf16)v;
@@ -206,7 +227,8 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
             auto step = [&](const bf16x8 (&f)[4], int s) {
 #pragma unroll
                 for (int i = 0; i < kTile / 16; ++i) {
-                    const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + (16 * i + c16) * kHRow + 32 * s + 8 * q);
+                    const int r = 16 * i + c16;
+                    const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + r * kHRow + h_chunk(r, 4 * s + q));
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[j][i] = mfma(f[j], hf, acc[j][i]);
                 }
@@ -220,7 +242,8 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
             __syncthreads();   // H of the previous layer complete
 #pragma unroll
             for (int i = 0; i < kTile / 16; ++i) {
-                const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + (16 * i + c16) * kHRow + 8 * q);
+                const int r = 16 * i + c16;
+                const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + r * kHRow + h_chunk(r, q));
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[j][i] = mfma(wa[j], hf, b[j]);
             }
@@ -252,8 +275,8 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 3) void mlp_infer_kernel(Inf
             const bf16x8 wf = *reinterpret_cast<const bf16x8*>(P + kPkOffOut + ((size_t)s * 64 + lane) * 8);
 #pragma unroll
             for (int i = 0; i < OT; ++i) {
-                const bf16x8 hf =
-                    *reinterpret_cast<const bf16x8*>(H + (16 * (OT * w + i) + c16) * kHRow + 32 * s + 8 * q);
+                const int r = 16 * (OT * w + i) + c16;
+                const bf16x8 hf = *reinterpret_cast<const bf16x8*>(H + r * kHRow + h_chunk(r, 4 * s + q));
                 o[i] = mfma(wf, hf, o[i]);
             }
         }

@@ -481,6 +481,129 @@ def context_main(args):
     return 0
 
 
+# Algorithmic FP64 work of the Mie series, counted from the operations the
+# series performs (complex multiply 6 flops, complex add 2, complex divide 12
+# with the real division as one flop): per downward step of a logarithmic
+# derivative D_n = n/z - 1/(D_{n+1} + n/z), 12; per upward term of a
+# homogeneous sphere (psi, xi recurrences, a_n and b_n, the three sums), 134;
+# a coated sphere adds 216 per term (G, T recurrences, U, V and the modified
+# ratios) and two more downward recurrences.
+MIE_FLOP_DOWN_STEP = 12
+MIE_FLOP_TERM = 134
+MIE_FLOP_TERM_COATED_EXTRA = 216
+FP64_PEAK = 78.6e12
+
+
+def mie_work(req):
+    """(size units, series terms, algorithmic FLOP) of a flat optics request,
+    with the series length and downward start of the device code."""
+    lam = np.asarray(req["lam"], np.float64)
+    offs = np.asarray(req["offsets"], np.int64)
+    cell = np.repeat(np.arange(len(lam)), np.diff(offs))
+    k0 = 2.0 * np.pi / lam[cell]
+    n_m = np.asarray(req["n_m"], np.float64)[cell]
+    k_m = np.asarray(req["k_m"], np.float64)[cell]
+    n_p = np.asarray(req["n_p"], np.float64)
+    k_p = np.asarray(req["k_p"], np.float64)
+    r = np.asarray(req["r"], np.float64)
+    if req.get("sd") is not None:   # the 101 diameters of each spread, positive ones only
+        d = (2.0 * r)[:, None] + np.asarray(req["sd"], np.float64)[:, None] * np.linspace(-3.0, 3.0, 101)[None, :]
+        keep = d > 0
+        rows = np.nonzero(keep)[0]
+        r = 0.5 * d[keep]
+        k0, n_m, k_m, n_p, k_p = (a[rows] for a in (k0, n_m, k_m, n_p, k_p))
+    mag = np.hypot(n_p, k_p)
+    ay = k0 * r * mag
+    coated = req.get("r_core") is not None
+    if coated:
+        rc = np.asarray(req["r_core"], np.float64)
+        ay = np.maximum(ay, k0 * rc * np.hypot(req["n_core"], req["k_core"]))
+    nn = np.ceil(2.0 + ay + 4.3 * np.cbrt(ay)).astype(np.int64) + 1
+    y2 = k0 * r * mag                                   # |m2 x| at the outer radius
+    nstart = np.maximum(nn, np.ceil(y2).astype(np.int64)) + 16
+    flop = MIE_FLOP_TERM * nn + MIE_FLOP_DOWN_STEP * nstart
+    if coated:
+        flop = flop + MIE_FLOP_TERM_COATED_EXTRA * nn + 2 * MIE_FLOP_DOWN_STEP * nstart
+    return len(r), int(nn.sum()), float(flop.sum())
+
+
+def optics_main(args):
+    """Per-entry GPU optics (Mie + effective medium, FP64) on three synthetic
+    request shapes: homogeneous spheres (the headline line), hollow coated
+    spheres, and 101-size Gaussian spreads.  Each is timed over `steps` calls
+    of fos_optics_run (HIP events on the current stream), against the FP64
+    oracle on the same request (all host threads)."""
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    import torch
+    import oracle
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    stream = torch.cuda.current_stream()
+    kinds = {}
+    for kind in W.MIE_KINDS:
+        req = W.mie_sweep(kind)
+        op = fos.OpticsProblem.from_request(req, "cuda")
+        C = op.n_cells
+        outs = [torch.zeros(C, dtype=torch.float32, device="cuda") for _ in range(3)]
+        for _ in range(max(args.warmup, 1)):
+            fos.fos_optics_run(h, op, *outs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fos.fos_optics_run(h, op, *outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) / 1e3 / args.steps
+        units, terms, flop = mie_work(req)
+        rec = {"cells": C, "entries": op.n_entries, "size_units": units, "series_terms": terms,
+               "seconds_per_call": dt, "units_per_s": units / dt, "terms_per_s": terms / dt,
+               "algorithmic_flop": flop, "fp64_tflops": flop / dt / 1e12, "frac_fp64_peak": flop / dt / FP64_PEAK}
+        say(f"{kind}: {C} cells, {units} size units, {terms} series terms: {dt * 1e3:.2f} ms per call, "
+            f"{units / dt:.3e} Mie evaluations/s, {flop / dt / 1e12:.2f} TFLOP/s FP64 (algorithmic)")
+        if not args.no_cpu_baseline:
+            # the oracle on the whole request, all host threads
+            threads = oracle.default_threads()
+            t0 = time.perf_counter()
+            ref = oracle.optics_batch(req, threads)
+            dto = time.perf_counter() - t0
+            got = torch.stack(outs, 1).cpu().numpy().astype(np.float64)
+            ext = np.maximum(ref[:, 0] + ref[:, 1], 1e-300)
+            rel = float((np.abs(got[:, :2] - ref[:, :2]) / ext[:, None]).max())
+            rec["cpu_baseline"] = {"value": units / dto, "unit": "Mie evaluations/s", "cores": threads,
+                                   "kind": "oracle", "sample": f"the whole request ({C} cells, {units} size "
+                                   f"units), FP64, {dto:.2f} s", "cpu": _cpu_model()}
+            rec["max_rel_error_vs_oracle"] = rel
+            say(f"{kind}: oracle {units / dto:.3e} Mie evaluations/s on {threads} threads; "
+                f"float outputs vs oracle, max error relative to extinction {rel:.1e}")
+        kinds[kind] = rec
+    head = kinds["homogeneous"]
+    out = {"metric": "Mie evaluations/s (per-entry GPU optics: Mie series + effective medium, FP64)",
+           "value": head["units_per_s"], "unit": "Mie evaluations/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * head["seconds_per_call"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "mie_sweep homogeneous: 2000 cells x 500 spheres (radius 0.01-2 um log-uniform, "
+                                  "wavelength 0.3-16 um); also coated (2000 x 50) and 101-size spreads (2000 x 5)",
+                      "items": head["entries"]},
+           "roofline": {"bound": "alu", "achieved": head["fp64_tflops"], "peak": FP64_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": head["frac_fp64_peak"], "traffic": None,
+                        "kernel": "fos::mie_entries (whole fos_optics_run timed)",
+                        "work_per_term_flop": MIE_FLOP_TERM, "work_per_down_step_flop": MIE_FLOP_DOWN_STEP},
+           "kinds": kinds, "wall_s": time.perf_counter() - t_start}
+    if "cpu_baseline" in head:
+        out["cpu_baseline"] = head["cpu_baseline"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def weighted_main(args):
     """Analog against weighted-packet walk on the two-species 500-wavelength
     slab: throughput of each, and the efficiency of the absorptance estimate,
@@ -560,11 +683,12 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
     ap.add_argument("--workload", default="two_species_500",
-                    choices=["two_species_500", "stacks_3layer", "surrogate", "paper_context", "weighted"],
+                    choices=["two_species_500", "stacks_3layer", "surrogate", "paper_context", "weighted", "optics"],
                     help="two_species_500 (default, the headline line), stacks_3layer (batched sweep), "
                          "surrogate (training on walk labels + design sweep with Monte Carlo fallback) or "
                          "paper_context (a run shaped like the paper's desktop timing, GPU and oracle) or "
-                         "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency)")
+                         "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency) or "
+                         "optics (per-entry GPU Mie + effective medium: homogeneous, coated, spread)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-photons", type=int, default=100_000)
     ap.add_argument("--epochs", type=int, default=60)
@@ -597,6 +721,8 @@ def main(argv=None):
         return context_main(args)
     if args.workload == "weighted":
         return weighted_main(args)
+    if args.workload == "optics":
+        return optics_main(args)
 
     import torch
     from paper_2409_00165_amd import fos

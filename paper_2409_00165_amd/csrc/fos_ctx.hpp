@@ -72,6 +72,8 @@ struct fos_ctx {
     size_t mie_bytes = 0;
     double2* mie_scratch = nullptr;
     size_t mie_scratch_bytes = 0;
+    unsigned int* mie_order = nullptr;        // size units by series length, class counts, classes
+    size_t mie_order_bytes = 0;
     double* ln_buf = nullptr;                 // log-normal grid cells, radii, weights, bin-sum table
     size_t ln_buf_bytes = 0;
     unsigned int* nmax_dev = nullptr;        // device, 1 word

@@ -76,6 +76,8 @@ struct OpticsArgs {
     int d_arrays;                 // logarithmic-derivative arrays per thread in scratch: 1, or 3 with cores
     unsigned int* flags;          // kOptHas* (optics_scan)
     double2* scratch;             // [(nn_cap + 1) * mie threads]
+    const unsigned int* order;    // size units by series length (null = unit order)
+    unsigned long long* queue;    // next position of the order to hand out (zeroed before mie_entries)
     unsigned int* nmax;           // largest series length + 1
     int nn_cap;
     unsigned long long* err;
@@ -107,6 +109,11 @@ hipError_t launch_lognormal_cells(const LognormalArgs& a, hipStream_t st);
 
 hipError_t launch_optics_scan(const OpticsArgs& a, hipStream_t st);
 hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st);
+// Size units sorted by series length, so that the lanes of a wave run
+// series of similar length; buf holds mie_order_bytes(n_units) bytes and
+// starts with the order (n_units words).  Needs a.cell_of (optics_scan).
+size_t mie_order_bytes(int64_t n_units);
+hipError_t launch_mie_order(const OpticsArgs& a, int64_t n_units, void* buf, hipStream_t st);
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);
 
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);

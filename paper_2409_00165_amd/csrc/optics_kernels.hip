@@ -4,14 +4,16 @@
 // host, eqs. (1)-(5), (10)-(12), (15), then the effective medium of every
 // layer cell, eqs. (13)-(20).  Double precision throughout.
 //
-//   optics_scan : per cell -- validate, record the owning cell of each
-//                 particle entry, and the largest Mie series length.
-//   mie_entries : grid-stride over particle entries; per entry the
+//   optics_scan : one wave per cell -- validate, record the owning cell of
+//                 each particle entry, and the largest Mie series length.
+//   order_units : the size units ordered by series length within contiguous
+//                 ranges, so the lanes of a wave run series of similar length.
+//   mie_entries : grid-stride over the sorted size units; per unit the
 //                 logarithmic derivative D_n(m x) by downward recurrence (kept
 //                 in a strided global scratch), psi_n(x) and xi_n(x) by upward
 //                 recurrence, a_n and b_n in the Bohren-Huffman form, and the
 //                 three series of eqs. (11), (12), (15).
-//   emt_cells   : per cell -- eqs. (13)-(16), the clamp, the dependent-
+//   emt_cells   : one wave per cell -- eqs. (13)-(16), the clamp, the dependent-
 //                 scattering factor (17)-(19) and matrix absorption (20).
 //   lognormal_* : log-normal populations whose bins lie on one radius grid:
 //                 per (species, matrix, wavelength, median radius) the bin
@@ -24,6 +26,7 @@
 #include <stdint.h>
 
 #include "fos_kernels.hpp"
+
 
 namespace fos {
 
@@ -65,51 +68,69 @@ __device__ __forceinline__ double spread_diameter(double d0, double sd, int sub)
     return d0 - 3.0 * sd + 6.0 * sd * (double)sub / (double)(kSpreadSizes - 1);
 }
 
+// Validation and series bound: one wave per cell, its lanes striding over the
+// cell's particle entries (cells may hold hundreds), then a wave reduction of
+// the longest series and of the kind flags.
 __global__ void optics_scan(OpticsArgs a)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n_cells) return;
+    const int lane = threadIdx.x & 63;
+    const int c = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (c >= a.n_cells) return;   // whole waves
     const double lam = a.lam[c], nm = a.n_m[c], km = a.k_m[c];
     const int64_t b = a.offsets[c], e = a.offsets[c + 1];
     bool bad = false;
-    if (!(lam > 0.0) || !isfinite(lam)) { optics_report(a.err, c, kOptErrLambda); bad = true; }
-    if (!(nm > 0.0) || !isfinite(nm)) { optics_report(a.err, c, kOptErrNm); bad = true; }
-    if (!(km >= 0.0) || !isfinite(km)) { optics_report(a.err, c, kOptErrKm); bad = true; }
-    if (b < 0 || e < b || e > a.n_entries) { optics_report(a.err, c, kOptErrOffsets); return; }
+    if (!(lam > 0.0) || !isfinite(lam)) { if (lane == 0) optics_report(a.err, c, kOptErrLambda); bad = true; }
+    if (!(nm > 0.0) || !isfinite(nm)) { if (lane == 0) optics_report(a.err, c, kOptErrNm); bad = true; }
+    if (!(km >= 0.0) || !isfinite(km)) { if (lane == 0) optics_report(a.err, c, kOptErrKm); bad = true; }
+    if (b < 0 || e < b || e > a.n_entries) {
+        if (lane == 0) optics_report(a.err, c, kOptErrOffsets);
+        return;
+    }
     if (bad) return;
     int nmax = 0;
     unsigned int flags = 0u;
     const double two_pi = 2.0 * 3.141592653589793;
-    for (int64_t j = b; j < e; ++j) {
+    for (int64_t j = b + lane; j < e; j += 64) {
         const double np_ = a.n_p[j], kp = a.k_p[j], r = a.r[j], f = a.f[j];
         const double sd = a.sd ? a.sd[j] : 0.0;
         const double rc = a.r_core ? a.r_core[j] : 0.0;
-        if (!(np_ > 0.0) || !isfinite(np_)) { optics_report(a.err, c, kOptErrNp); return; }
-        if (!(kp >= 0.0) || !isfinite(kp)) { optics_report(a.err, c, kOptErrKp); return; }
-        if (!(r > 0.0) || !isfinite(r)) { optics_report(a.err, c, kOptErrRadius); return; }
-        if (!(f >= 0.0) || !isfinite(f)) { optics_report(a.err, c, kOptErrFraction); return; }
-        if (!(sd >= 0.0) || !isfinite(sd)) { optics_report(a.err, c, kOptErrSpread); return; }
-        if (!(rc >= 0.0) || !(rc <= r)) { optics_report(a.err, c, kOptErrCore); return; }
-        if (sd > 0.0 && rc > 0.0) { optics_report(a.err, c, kOptErrSpreadCore); return; }
+        int code = 0;
+        if (!(np_ > 0.0) || !isfinite(np_)) code = kOptErrNp;
+        else if (!(kp >= 0.0) || !isfinite(kp)) code = kOptErrKp;
+        else if (!(r > 0.0) || !isfinite(r)) code = kOptErrRadius;
+        else if (!(f >= 0.0) || !isfinite(f)) code = kOptErrFraction;
+        else if (!(sd >= 0.0) || !isfinite(sd)) code = kOptErrSpread;
+        else if (!(rc >= 0.0) || !(rc <= r)) code = kOptErrCore;
+        else if (sd > 0.0 && rc > 0.0) code = kOptErrSpreadCore;
+        else if (rc > 0.0) {
+            const double nc = a.n_core[j], kc = a.k_core[j];
+            if (!(nc > 0.0) || !isfinite(nc) || !(kc >= 0.0) || !isfinite(kc)) code = kOptErrCore;
+        }
+        if (code != 0) {
+            optics_report(a.err, c, code);
+            break;
+        }
         a.cell_of[j] = c;
         // |y| of eq. (1) for the largest size of the entry, at the larger index
         double ay = two_pi * (sd > 0.0 ? 0.5 * spread_diameter(2.0 * r, sd, kSpreadSizes - 1) : r) *
                     sqrt(np_ * np_ + kp * kp) / lam;
         if (rc > 0.0) {
-            const double nc = a.n_core[j], kc = a.k_core[j];
-            if (!(nc > 0.0) || !isfinite(nc) || !(kc >= 0.0) || !isfinite(kc)) {
-                optics_report(a.err, c, kOptErrCore);
-                return;
-            }
-            ay = fmax(ay, two_pi * rc * sqrt(nc * nc + kc * kc) / lam);
+            ay = fmax(ay, two_pi * rc * sqrt(a.n_core[j] * a.n_core[j] + a.k_core[j] * a.k_core[j]) / lam);
             flags |= kOptHasCore;
         }
         if (sd > 0.0) flags |= kOptHasSpread;
         const int nn = series_length(ay) + 1;
         if (nn > nmax) nmax = nn;
     }
-    if (nmax > 0) atomicMax(a.nmax, (unsigned int)nmax);
-    if (flags) atomicOr(a.flags, flags);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        nmax = max(nmax, __shfl_xor(nmax, o));
+        flags |= (unsigned int)__shfl_xor((int)flags, o);
+    }
+    if (lane == 0) {
+        if (nmax > 0) atomicMax(a.nmax, (unsigned int)nmax);
+        if (flags) atomicOr(a.flags, flags);
+    }
 }
 
 // D_n(z), n = 1..nn, by downward recurrence from far above, stored strided
@@ -244,8 +265,85 @@ __device__ Series mie_series(double lam, cd Nm, cd Ns, double r, bool coated, cd
     return S;
 }
 
+// Size units ordered by series length within contiguous ranges of about
+// kOrderRange units, one block per range: a class histogram in LDS (class =
+// series length, capped at kOrderClasses - 1), its exclusive prefix, then
+// every unit placed at its class offset plus its rank.  With ranges this
+// long a class holds dozens of units, so 64 neighbouring positions of the
+// order hold series of nearly equal length, which is what the lanes of a
+// wave need.  The order within a class is not fixed, and need not be: each
+// unit's result is written at its own index.
+constexpr int kOrderClasses = 1024;
+#ifndef FOS_ORDER_RANGE
+#define FOS_ORDER_RANGE 4096
+#endif
+constexpr int64_t kOrderRange = FOS_ORDER_RANGE;
+
+__device__ __forceinline__ int unit_class(const OpticsArgs& a, int64_t u)
+{
+    const double two_pi = 2.0 * 3.141592653589793;
+    const int64_t j = u / a.units;
+    const int sub = (int)(u % a.units);
+    const double sd = a.sd ? a.sd[j] : 0.0;
+    const double rc = a.r_core ? a.r_core[j] : 0.0;
+    double r = a.r[j];
+    if (sd > 0.0) {
+        const double d = spread_diameter(2.0 * r, sd, sub);
+        if (!(d > 0.0)) return 0;   // skipped by mie_entries
+        r = 0.5 * d;
+    } else if (sub > 0) {
+        return 0;
+    }
+    const double lam = a.lam[a.cell_of[j]];
+    double ay = two_pi * r * sqrt(a.n_p[j] * a.n_p[j] + a.k_p[j] * a.k_p[j]) / lam;
+    if (rc > 0.0) ay = fmax(ay, two_pi * rc * sqrt(a.n_core[j] * a.n_core[j] + a.k_core[j] * a.k_core[j]) / lam);
+    const int nn = series_length(ay) + 1;
+    return nn < kOrderClasses ? nn : kOrderClasses - 1;
+}
+
+__global__ __launch_bounds__(256) void order_units(OpticsArgs a, int64_t n_units, int64_t per_block,
+                                                   unsigned short* cls, unsigned int* order)
+{
+    __shared__ unsigned int next[kOrderClasses];
+    __shared__ unsigned int part[256];
+    const int t = threadIdx.x;
+    for (int k = t; k < kOrderClasses; k += 256) next[k] = 0u;
+    __syncthreads();
+    const int64_t u0 = (int64_t)blockIdx.x * per_block;
+    const int64_t u1 = u0 + per_block < n_units ? u0 + per_block : n_units;
+    for (int64_t u = u0 + t; u < u1; u += 256) {
+        const int k = kOrderClasses - 1 - unit_class(a, u);   // longest series first
+        cls[u] = (unsigned short)k;
+        atomicAdd(&next[k], 1u);
+    }
+    __syncthreads();
+    // exclusive prefix of the histogram: 4 classes per thread, then across threads
+    constexpr int per = kOrderClasses / 256;
+    unsigned int c[per], sum = 0u;
+#pragma unroll
+    for (int i = 0; i < per; ++i) { c[i] = next[per * t + i]; sum += c[i]; }
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const unsigned int v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned int run = (unsigned int)u0 + part[t] - sum;
+#pragma unroll
+    for (int i = 0; i < per; ++i) { next[per * t + i] = run; run += c[i]; }
+    __syncthreads();
+    for (int64_t u = u0 + t; u < u1; u += 256) {
+        const unsigned int pos = atomicAdd(&next[cls[u]], 1u);
+        order[pos] = (unsigned int)u;
+    }
+}
+
 // One thread per size unit (entry, sub): Gaussian spreads give 101 units per
-// entry (unused units are skipped), everything else one.
+// entry (unused units are skipped), everything else one.  Waves claim 64
+// consecutive positions of the order (a.order, else unit order) at a time
+// from a queue counter.
 __global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
 {
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -253,7 +351,17 @@ __global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
     const double pi = 3.141592653589793;
     const size_t n_units = (size_t)a.n_entries * a.units;
     const size_t dstride = ((size_t)a.nn_cap + 1) * nthreads;
-    for (size_t u = tid; u < n_units; u += nthreads) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        // each wave takes the next 64 positions of the order from the queue,
+        // so waves that drew short series take more of them
+        unsigned long long base = 0ull;
+        if (lane == 0) base = atomicAdd(a.queue, 64ull);
+        base = __shfl(base, 0);
+        if (base >= n_units) break;
+        const size_t s = (size_t)base + lane;
+        if (s >= n_units) continue;
+        const size_t u = a.order ? (size_t)a.order[s] : s;
         const size_t j = u / a.units;
         const int sub = (int)(u % a.units);
         const int c = a.cell_of[j];
@@ -290,28 +398,45 @@ __global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
     }
 }
 
+// Effective medium of each cell, eqs. (13)-(20): one wave per cell.  Lanes
+// stride over the cell's entries; an entry with a Gaussian spread is taken
+// by the whole wave, its 101 diameters across the lanes (the weight
+// normalisation is a wave sum).  Partial sums are reduced across the wave.
 __global__ void emt_cells(OpticsArgs a)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n_cells) return;
+    const int lane = threadIdx.x & 63;
+    const int c = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (c >= a.n_cells) return;   // whole waves
     const int64_t b = a.offsets[c], e = a.offsets[c + 1];
     double mus = 0.0, mua = 0.0, gs = 0.0, F = 0.0;
-    for (int64_t j = b; j < e; ++j) {
+    for (int64_t j = b + lane; j < e; j += 64) {
         const double f = a.f[j];
-        const double sd = a.sd ? a.sd[j] : 0.0;
-        const double* q = a.mie + 3 * (size_t)j * a.units;
         F += f;
-        if (sd > 0.0) {
+        if (a.sd && a.sd[j] > 0.0) continue;   // below
+        const double* q = a.mie + 3 * (size_t)j * a.units;
+        const double r = a.r[j];
+        const double ws = 1.5 * q[1] * f / (2.0 * r);
+        mus += ws;
+        mua += 1.5 * (q[0] - q[1]) * f / (2.0 * r);
+        gs += ws * q[2];
+    }
+    if (a.sd) {
+        for (int64_t j = b; j < e; ++j) {
+            const double sd = a.sd[j];
+            if (!(sd > 0.0)) continue;
             // Gaussian weights of the 101 diameters, renormalised over the positive ones
-            const double d0 = 2.0 * a.r[j];
+            const double d0 = 2.0 * a.r[j], f = a.f[j];
+            const double* q = a.mie + 3 * (size_t)j * a.units;
             double wsum = 0.0;
-            for (int k = 0; k < kSpreadSizes; ++k) {
+            for (int k = lane; k < kSpreadSizes; k += 64) {
                 const double d = spread_diameter(d0, sd, k);
                 if (!(d > 0.0)) continue;
                 const double z = (d - d0) / sd;
                 wsum += exp(-0.5 * z * z);
             }
-            for (int k = 0; k < kSpreadSizes; ++k) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+            for (int k = lane; k < kSpreadSizes; k += 64) {
                 const double d = spread_diameter(d0, sd, k);
                 if (!(d > 0.0)) continue;
                 const double z = (d - d0) / sd;
@@ -322,14 +447,16 @@ __global__ void emt_cells(OpticsArgs a)
                 mua += 1.5 * (qk[0] - qk[1]) * fk / (2.0 * rk);
                 gs += ws * qk[2];
             }
-        } else {
-            const double r = a.r[j];
-            const double ws = 1.5 * q[1] * f / (2.0 * r);
-            mus += ws;
-            mua += 1.5 * (q[0] - q[1]) * f / (2.0 * r);
-            gs += ws * q[2];
         }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mus += __shfl_xor(mus, o);
+        mua += __shfl_xor(mua, o);
+        gs += __shfl_xor(gs, o);
+        F += __shfl_xor(F, o);
+    }
+    if (lane != 0) return;
     double g = mus > 0.0 ? gs / mus : 0.0;
     if (mus < 0.0) mus = 0.0;
     if (mua < 0.0) mua = 0.0;
@@ -436,7 +563,7 @@ hipError_t launch_lognormal_cells(const LognormalArgs& a, hipStream_t st)
 hipError_t launch_optics_scan(const OpticsArgs& a, hipStream_t st)
 {
     if (a.n_cells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(optics_scan, dim3((a.n_cells + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(optics_scan, dim3((unsigned)(((size_t)a.n_cells * 64 + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -447,10 +574,27 @@ hipError_t launch_mie(const OpticsArgs& a, int grid, int block, hipStream_t st)
     return hipGetLastError();
 }
 
+size_t mie_order_bytes(int64_t n_units)
+{
+    return (size_t)n_units * (sizeof(unsigned int) + sizeof(unsigned short)) + 256;
+}
+
+hipError_t launch_mie_order(const OpticsArgs& a, int64_t n_units, void* buf, hipStream_t st)
+{
+    if (n_units <= 0) return hipSuccess;
+    int64_t blocks = (n_units + kOrderRange - 1) / kOrderRange;
+    if (blocks > 65535) blocks = 65535;
+    const int64_t per_block = (n_units + blocks - 1) / blocks;
+    unsigned int* order = reinterpret_cast<unsigned int*>(buf);
+    unsigned short* cls = reinterpret_cast<unsigned short*>(order + n_units);
+    hipLaunchKernelGGL(order_units, dim3((unsigned)blocks), dim3(256), 0, st, a, n_units, per_block, cls, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st)
 {
     if (a.n_cells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(emt_cells, dim3((a.n_cells + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(emt_cells, dim3((unsigned)(((size_t)a.n_cells * 64 + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -135,6 +135,7 @@ void fos_destroy(fos_ctx* c)
         if (c->cell_of) (void)hipFree(c->cell_of);
         if (c->mie) (void)hipFree(c->mie);
         if (c->mie_scratch) (void)hipFree(c->mie_scratch);
+        if (c->mie_order) (void)hipFree(c->mie_order);
         if (c->ln_buf) (void)hipFree(c->ln_buf);
         if (c->tune_tallies) (void)hipFree(c->tune_tallies);
         if (c->seed_dev) (void)hipFree(c->seed_dev);
@@ -557,6 +558,17 @@ fos_status fos_optics_run(fos_ctx* c, const fos_optics_problem* p, float* mu_s, 
                   (size_t)a.d_arrays * ((size_t)a.nn_cap + 1) * nthreads * sizeof(double2))) != hipSuccess)
         return hip_fail(c, e, "Mie scratch");
     a.scratch = c->mie_scratch;
+    // size units sorted by series length when there are enough to matter
+    a.order = nullptr;
+    const int64_t n_units = P * a.units;
+    if (n_units > 4096 && n_units < 0xFFFFFFFFll) {
+        if ((e = grow(c->mie_order, c->mie_order_bytes, fos::mie_order_bytes(n_units))) != hipSuccess)
+            return hip_fail(c, e, "Mie order scratch");
+        if ((e = fos::launch_mie_order(a, n_units, c->mie_order, st)) != hipSuccess) return hip_fail(c, e, "Mie order");
+        a.order = c->mie_order;
+    }
+    a.queue = c->err_dev + 4;
+    if ((e = fos::launch_fill_u64(a.queue, 0ull, 1, st)) != hipSuccess) return hip_fail(c, e, "Mie queue");
     if ((e = fos::launch_mie(a, grid, block, st)) != hipSuccess) return hip_fail(c, e, "Mie kernel");
     if ((e = fos::launch_emt(a, st)) != hipSuccess) return hip_fail(c, e, "effective-medium kernel");
     return FOS_OK;

@@ -496,3 +496,51 @@ def planck_weights(lam: np.ndarray, temperature: float, lo: float, hi: float) ->
         w[a] += 0.5 * h * B[a]
         w[b] += 0.5 * h * B[b]
     return w / w.sum()
+
+
+MIE_KINDS = ("homogeneous", "coated", "spread")
+
+
+def mie_sweep(kind: str, n_cells: int = 2000, seed: int = 20240902) -> dict:
+    """A flat optics request (the format of optics_request) for timing the
+    per-entry Mie path.  Cells: wavelengths log-uniform in 0.3..16 um,
+    matrix index U[1.3, 1.7] with k_m = 1e-4.  Entries per cell, species A or
+    B with equal odds at f = 1e-4 each:
+      homogeneous: 500 spheres, radius log-uniform in 0.01..2 um;
+      coated:      50 hollow particles (air core, species-B shell), outer
+                   radius log-uniform in 0.05..1 um, core 50..90 % of it;
+      spread:      5 populations with the 101-size Gaussian diameter spread,
+                   mean diameter log-uniform in 0.05..2 um, standard deviation
+                   10 % of it.
+    """
+    if kind not in MIE_KINDS:
+        raise ValueError(f"kind must be one of {MIE_KINDS}")
+    rng = np.random.default_rng(seed + MIE_KINDS.index(kind))
+    per = {"homogeneous": 500, "coated": 50, "spread": 5}[kind]
+    lam = np.exp(rng.uniform(np.log(0.3), np.log(16.0), n_cells))
+    n_m = rng.uniform(1.3, 1.7, n_cells)
+    k_m = np.full(n_cells, 1e-4)
+    P = n_cells * per
+    cell = np.repeat(np.arange(n_cells), per)
+    species_b = rng.uniform(size=P) < 0.5
+    na, ka = species_a_index(lam[cell])
+    nb, kb = species_b_index(lam[cell])
+    n_p = np.where(species_b, nb, na)
+    k_p = np.where(species_b, kb, ka)
+    out = {"cells": n_cells, "max_layers": 1, "lam": lam, "n_m": n_m, "k_m": k_m,
+           "offsets": np.arange(n_cells + 1, dtype=np.int64) * per, "f": np.full(P, 1e-4)}
+    if kind == "homogeneous":
+        out["r"] = np.exp(rng.uniform(np.log(0.01), np.log(2.0), P))
+    elif kind == "coated":
+        r = np.exp(rng.uniform(np.log(0.05), np.log(1.0), P))
+        out["r"] = r
+        out["r_core"] = r * rng.uniform(0.5, 0.9, P)
+        nc, kc = air_index(lam[cell])
+        out["n_core"], out["k_core"] = nc, kc
+        n_p, k_p = nb, kb
+    else:
+        d = np.exp(rng.uniform(np.log(0.05), np.log(2.0), P))
+        out["r"] = 0.5 * d
+        out["sd"] = 0.1 * d
+    out["n_p"], out["k_p"] = n_p, k_p
+    return out

@@ -77,7 +77,7 @@ struct OpticsArgs {
     unsigned int* flags;          // kOptHas* (optics_scan)
     double2* scratch;             // [(nn_cap + 1) * mie threads]
     const unsigned int* order;    // size units by series length (null = unit order)
-    unsigned long long* queue;    // next position of the order to hand out (zeroed before mie_entries)
+    unsigned long long* queue;    // next 64-unit claim of mie_entries to hand out (zeroed before it)
     unsigned int* nmax;           // largest series length + 1
     int nn_cap;
     unsigned long long* err;

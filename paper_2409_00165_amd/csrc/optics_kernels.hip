@@ -8,7 +8,8 @@
 //                 each particle entry, and the largest Mie series length.
 //   order_units : the size units ordered by series length within contiguous
 //                 ranges, so the lanes of a wave run series of similar length.
-//   mie_entries : grid-stride over the sorted size units; per unit the
+//   mie_entries : waves claim 64 sorted size units at a time, taking the
+//                 ranges in turn so the longest series start first; per unit the
 //                 logarithmic derivative D_n(m x) by downward recurrence (kept
 //                 in a strided global scratch), psi_n(x) and xi_n(x) by upward
 //                 recurrence, a_n and b_n in the Bohren-Huffman form, and the
@@ -40,17 +41,26 @@ __device__ __forceinline__ cd operator*(cd a, cd b) { return cd{a.re * b.re - a.
 __device__ __forceinline__ cd operator*(double s, cd a) { return cd{s * a.re, s * a.im}; }
 __device__ __forceinline__ cd conj_(cd a) { return cd{a.re, -a.im}; }
 __device__ __forceinline__ double abs2(cd a) { return a.re * a.re + a.im * a.im; }
-// Smith's division
-__device__ __forceinline__ cd operator/(cd a, cd b)
+// 1/x for x in [1/4, 2]: the hardware estimate and two Newton steps (each
+// doubles the correct bits), a few ulp from the rounded quotient.
+__device__ __forceinline__ double rcp_near_one(double x)
 {
-    if (fabs(b.re) >= fabs(b.im)) {
-        const double r = b.im / b.re, d = b.re + b.im * r;
-        return cd{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
-    }
-    const double r = b.re / b.im, d = b.re * r + b.im;
-    return cd{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
 }
-__device__ __forceinline__ cd recip(cd b) { return mk(1.0, 0.0) / b; }
+// 1/b = conj(b) / |b|^2, with b first scaled by the power of two that brings
+// its larger part into [1/2, 1), so |b|^2 neither overflows nor underflows and
+// one reciprocal replaces the three divisions (and the branch) of Smith's
+// method.
+__device__ __forceinline__ cd recip(cd b)
+{
+    const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(b.re), fabs(b.im)));
+    const double br = ldexp(b.re, -e), bi = ldexp(b.im, -e);
+    const double q = rcp_near_one(br * br + bi * bi);
+    return cd{ldexp(br * q, -e), ldexp(-bi * q, -e)};
+}
+__device__ __forceinline__ cd operator/(cd a, cd b) { return a * recip(b); }
 __device__ __forceinline__ cd csin_(cd z) { return cd{sin(z.re) * cosh(z.im), cos(z.re) * sinh(z.im)}; }
 __device__ __forceinline__ cd ccos_(cd z) { return cd{cos(z.re) * cosh(z.im), -sin(z.re) * sinh(z.im)}; }
 
@@ -279,6 +289,15 @@ constexpr int kOrderClasses = 1024;
 #endif
 constexpr int64_t kOrderRange = FOS_ORDER_RANGE;
 
+// Units per ordered range for n_units units: about kOrderRange, one block of
+// order_units per range, at most 65535 ranges.
+__host__ __device__ __forceinline__ int64_t order_range(int64_t n_units)
+{
+    int64_t blocks = (n_units + kOrderRange - 1) / kOrderRange;
+    if (blocks > 65535) blocks = 65535;
+    return (n_units + blocks - 1) / blocks;
+}
+
 __device__ __forceinline__ int unit_class(const OpticsArgs& a, int64_t u)
 {
     const double two_pi = 2.0 * 3.141592653589793;
@@ -342,8 +361,12 @@ __global__ __launch_bounds__(256) void order_units(OpticsArgs a, int64_t n_units
 
 // One thread per size unit (entry, sub): Gaussian spreads give 101 units per
 // entry (unused units are skipped), everything else one.  Waves claim 64
-// consecutive positions of the order (a.order, else unit order) at a time
-// from a queue counter.
+// positions at a time from a queue counter.  Without an order the positions
+// are the units themselves.  With one (a.order: ranges of order_range units,
+// each longest series first) claim c takes chunk c / R of range c % R, R
+// ranges in all: the first chunks of every range come before the second of
+// any, so the longest series of the whole request start first and the short
+// ones fill the end.
 __global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
 {
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -352,15 +375,21 @@ __global__ __launch_bounds__(256) void mie_entries(OpticsArgs a)
     const size_t n_units = (size_t)a.n_entries * a.units;
     const size_t dstride = ((size_t)a.nn_cap + 1) * nthreads;
     const int lane = threadIdx.x & 63;
+    const size_t range = a.order ? (size_t)order_range((int64_t)n_units) : n_units;
+    const size_t n_ranges = (n_units + range - 1) / range;
+    const size_t n_claims = n_ranges * ((range + 63) / 64);
     for (;;) {
-        // each wave takes the next 64 positions of the order from the queue,
-        // so waves that drew short series take more of them
-        unsigned long long base = 0ull;
-        if (lane == 0) base = atomicAdd(a.queue, 64ull);
-        base = __shfl(base, 0);
-        if (base >= n_units) break;
-        const size_t s = (size_t)base + lane;
-        if (s >= n_units) continue;
+        // each wave takes the next chunk from the queue, so waves that drew
+        // short series take more of them
+        unsigned long long claim = 0ull;
+        if (lane == 0) claim = atomicAdd(a.queue, 1ull);
+        claim = __shfl(claim, 0);
+        if (claim >= n_claims) break;
+        const size_t rg = (size_t)claim % n_ranges;
+        const size_t r0 = rg * range;
+        const size_t r1 = r0 + range < n_units ? r0 + range : n_units;
+        const size_t s = r0 + 64 * ((size_t)claim / n_ranges) + lane;
+        if (s >= r1) continue;
         const size_t u = a.order ? (size_t)a.order[s] : s;
         const size_t j = u / a.units;
         const int sub = (int)(u % a.units);
@@ -582,9 +611,8 @@ size_t mie_order_bytes(int64_t n_units)
 hipError_t launch_mie_order(const OpticsArgs& a, int64_t n_units, void* buf, hipStream_t st)
 {
     if (n_units <= 0) return hipSuccess;
-    int64_t blocks = (n_units + kOrderRange - 1) / kOrderRange;
-    if (blocks > 65535) blocks = 65535;
-    const int64_t per_block = (n_units + blocks - 1) / blocks;
+    const int64_t per_block = order_range(n_units);
+    const int64_t blocks = (n_units + per_block - 1) / per_block;
     unsigned int* order = reinterpret_cast<unsigned int*>(buf);
     unsigned short* cls = reinterpret_cast<unsigned short*>(order + n_units);
     hipLaunchKernelGGL(order_units, dim3((unsigned)blocks), dim3(256), 0, st, a, n_units, per_block, cls, order);

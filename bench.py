@@ -76,6 +76,24 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def _gpu_info(device: int = 0) -> dict:
+    """Name, architecture, compute units and the peak engine / memory clocks
+    the HIP runtime reports for the device."""
+    import ctypes
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    info = {"name": p.name, "arch": p.gcnArchName, "compute_units": p.multi_processor_count}
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        for key, attr in (("peak_clock_mhz", 5), ("memory_clock_mhz", 60)):   # hipDeviceAttribute{,Memory}ClockRate
+            v = ctypes.c_int(0)
+            if hip.hipDeviceGetAttribute(ctypes.byref(v), attr, device) == 0:
+                info[key] = v.value / 1000.0
+    except OSError:
+        pass
+    return info
+
+
 def gpu_problem(ctx, wl, device="cuda"):
     """Optics on the GPU, then the transport problem as device tensors."""
     import torch
@@ -795,7 +813,10 @@ def main(argv=None):
         "spectra_per_s": args.steps / elapsed,
         "mean_steps_per_photon": steps_total / photons_total,
         "walk_kernel_ms": float(walk_ms.mean()),
+        "walk_kernel_ms_median": float(np.median(walk_ms)),
         "walk_kernel_ms_all": [round(float(x), 3) for x in walk_ms],
+        "seed": args.seed,
+        "gpu": _gpu_info(0),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tslot/s", "frac": achieved / VALU_PEAK, "traffic": measured_traffic(),
                      "work_per_step_slots": STEP_SLOTS, "steps_per_launch": steps_per_launch,

@@ -72,6 +72,22 @@ def test_workload_optics_match_oracle(ctx, torch, orc, name):
     assert np.array_equal(got32, got64.astype(np.float32))
 
 
+@pytest.mark.parametrize("kind", W.MIE_KINDS)
+def test_mie_sweep_requests_full_size(ctx, torch, orc, kind):
+    """The three requests the optics benchmark times, at full size (2000
+    cells; 10^6 spheres, 10^5 hollow spheres, 10^4 populations x 101
+    diameters): every cell against the oracle.  With more than 4096 size units
+    they take the ordered path of the Mie kernel (ranges claimed in turn);
+    a second call gives the same bits."""
+    req = W.mie_sweep(kind)
+    ref = orc.optics_batch(req)
+    got64, got32 = _gpu_optics(ctx, torch, req)
+    _compare(ref, got64, f"mie_sweep {kind}", floor=_geometric_scale(req))
+    assert np.array_equal(got32, got64.astype(np.float32))
+    again, _ = _gpu_optics(ctx, torch, req)
+    assert np.array_equal(again, got64)
+
+
 def test_three_layer_designs_match_oracle(ctx, torch, orc):
     wl = W.stacks_3layer(n_designs=12, n_lambda=100)
     req = W.optics_request(wl)

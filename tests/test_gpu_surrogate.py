@@ -171,6 +171,45 @@ def test_prediction_spans_many_tiles_row_independently(ctx, torch):
     assert worst < 5e-3
 
 
+def test_prediction_at_full_sweep_size(ctx, torch):
+    """2e8 rows in one launch, the size of the paint sweep (10^6 designs x
+    200 wavelengths; 1,562,500 workgroups): the first and last 64 rows and 300
+    at random against the bf16-emulating oracle (ensemble mean and spread), and
+    the domain flag against the training box checked on the host."""
+    from paper_2409_00165_amd import fos
+    members, mean, std, lo, hi = _model(7)
+    fos.fos_sur_load(ctx, _blob(members, mean, std, lo, hi))
+    n = 200_000_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2024)
+    x = torch.randn(n, 8, device="cuda", generator=gen)
+    x.mul_(torch.from_numpy(std.astype(np.float32)).cuda()).add_(torch.from_numpy(mean.astype(np.float32)).cuda())
+    x[:, 7] = 0.0
+    rat = torch.zeros(n * 3, device="cuda")
+    spread = torch.zeros(n, device="cuda")
+    ind = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fos.fos_sur_predict(ctx, x.view(-1), rat=rat, spread=spread, in_domain=ind)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.arange(64), np.arange(n - 64, n),
+                           np.random.default_rng(13).choice(n, size=300, replace=False)])
+    ri = torch.from_numpy(rows).cuda()
+    xr = x[ri].cpu().numpy()
+    got_rat = rat.view(n, 3)[ri].cpu().numpy().astype(np.float64)
+    got_spread = spread[ri].cpu().numpy().astype(np.float64)
+    got_in = ind[ri].cpu().numpy()
+    del x, rat, spread, ind
+    torch.cuda.empty_cache()
+    xs = ((xr.astype(np.float64) - mean) / std).astype(np.float32).astype(np.float64)
+    em = np.stack([_emulated_forward(_as_gpu_weights(m), xs) for m in members])
+    d_rat = np.abs(got_rat - em.mean(0)).max()
+    d_spread = np.abs(got_spread - (em.max(0) - em.min(0)).max(1)).max()
+    print("2e8-row call, sampled rows vs bf16-emulating oracle: mean", d_rat, "spread", d_spread, flush=True)
+    assert d_rat < 5e-3 and d_spread < 1e-2
+    box = np.all((xr >= lo.astype(np.float32)) & (xr <= hi.astype(np.float32)), axis=1)
+    assert np.array_equal(got_in.astype(bool), box)
+    assert 0 < box.sum() < len(rows)
+
+
 def test_gate_domain_and_eligibility(ctx, torch):
     from paper_2409_00165_amd import fos
     members, mean, std, lo, hi = _model(1)

@@ -7,7 +7,7 @@ walk that the weighted form is for."""
 import numpy as np
 import pytest
 
-from gpu_helpers import device_problem, make_arrays, run_gpu
+from gpu_helpers import arrays_from_problem, device_problem, load_golden, make_arrays, run_gpu
 from test_oracle_walk import _adding_stack
 
 pytestmark = pytest.mark.gpu
@@ -90,6 +90,32 @@ def test_weighted_same_seed_tracks_the_oracle(ctx, torch, orc):
     d = np.abs(got - ref).max()
     print("weighted same-seed max |d|:", d, flush=True)
     assert d < 2e-3
+
+
+def test_weighted_full_size_matches_the_analog_oracle(ctx, torch):
+    """The benchmark workload (500 wavelengths x 1e6 photons) on the weighted
+    walk against the stored analog oracle tallies of the same problem: both
+    estimate the same R, A, T, so every channel agrees within 5 combined
+    standard errors (1,500 comparisons), and the sum of squared z stays near
+    its degrees of freedom.  The weighted side brings its own variance
+    estimate.  The analog side's binomial error is taken at the pooled
+    proportion: where transmission is 1e-7..1e-6, 1e6 analog photons often
+    transmit none, and an error estimated from that zero would be zero."""
+    G = load_golden("two_species_500")
+    a = arrays_from_problem(G["problem"])
+    o = np.asarray(G["tallies"], np.float64)
+    N = np.asarray(a["photons"], np.float64)[:, None]
+    _, got, se_g = _gpu_w(ctx, torch, a, seed=77)
+    po = np.stack([o[:, 0] + o[:, 1], o[:, 2], o[:, 3]], 1) / N
+    pbar = 0.5 * (po + got)
+    se = np.sqrt(se_g ** 2 + pbar * (1 - pbar) / N)
+    live = se > 0
+    assert np.all(np.abs(got - po)[~live] == 0)
+    z = np.abs(got - po)[live] / se[live]
+    chi2, dof = float((z ** 2).sum()), int(live.sum())
+    print(f"weighted full size vs analog oracle: worst z {z.max():.2f}, chi2 {chi2:.0f} over {dof}", flush=True)
+    assert z.max() <= 5.0
+    assert chi2 < dof + 6 * np.sqrt(2 * dof) + 10
 
 
 @pytest.mark.parametrize("case", [

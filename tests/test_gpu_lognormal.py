@@ -53,6 +53,27 @@ def test_lognormal_matches_oracle(ctx, torch, orc):
     assert e[0] < 1e-6 and e[1] < 1e-6 and e[2] < 1e-6
 
 
+def test_lognormal_full_sweep_sampled(ctx, torch, orc):
+    """The paint sweep at full size in one call (10^6 designs x 200
+    wavelengths = 2e8 cells): 64 designs drawn at random, all their
+    wavelengths, against the oracle's per-entry effective medium."""
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    L = 200
+    sweep = W.paint_sweep(1_000_000, n_lambda=L)
+    prob = SP.paint_problem(ctx, sweep)
+    assert prob.n_items == 1_000_000 * L
+    designs = np.sort(np.random.default_rng(21).choice(1_000_000, size=64, replace=False))
+    rows = torch.from_numpy((designs[:, None] * L + np.arange(L)[None, :]).ravel()).cuda()
+    got = np.stack([prob.tensors[k][rows].cpu().numpy().astype(np.float64) for k in ("mu_s", "mu_a", "g")], 1)
+    del prob
+    torch.cuda.empty_cache()
+    mus, mua, g = orc.workload_optics(sweep.workload(designs))
+    ref = np.stack([mus[:, 0], mua[:, 0], g[:, 0]], 1)
+    e = _errors(ref, got)
+    print("full sweep, 64 sampled designs vs oracle (float outputs):", e, flush=True)
+    assert e[0] < 1e-6 and e[1] < 1e-6 and e[2] < 1e-6
+
+
 def test_lognormal_equals_per_entry_path(ctx, torch):
     from paper_2409_00165_amd import surrogate_pipeline as SP
     sweep = W.paint_sweep(300, n_lambda=100, seed=6)

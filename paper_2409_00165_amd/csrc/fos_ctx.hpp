@@ -61,7 +61,9 @@ struct fos_ctx {
     unsigned long long* chunk_prefix = nullptr;    // [n_items + 1]
     size_t chunk_prefix_bytes = 0;
     unsigned long long* chunk_counter = nullptr;   // device, 1 word
-    unsigned long long* err_dev = nullptr;   // device, 1 word
+    // device, 32 words: [0] first validation error, [1] item-table verdict (prepare) /
+    // [2] optics kind flags, [4] Mie claim counter
+    unsigned long long* err_dev = nullptr;
     unsigned long long* err_host = nullptr;  // pinned host, 1 word
     fos_mc_launch defaults{};
 

@@ -115,7 +115,12 @@ typedef struct {
 } fos_mc_problem;
 
 /* Launch knobs of the persistent walk kernel; a zero field takes the
- * context's current default (set by fos_mc_autotune, else built-in). */
+ * context's current default (set by fos_mc_set_launch or fos_mc_autotune,
+ * else built-in).  Until a chunk default is set that way, a launch without a
+ * chunk sizes it per problem: the largest power of two at most
+ * n_items * (largest photon budget) / (4 * resident waves), within
+ * [256, built-in default 2048], so that small batches still give every wave
+ * several claims.  Tallies never depend on these knobs. */
 typedef struct {
     int32_t block_size;     /* threads per workgroup, multiple of 64, 64..1024   */
     int32_t refill_min;     /* refill a wave when >= this many lanes idle, 1..64 */

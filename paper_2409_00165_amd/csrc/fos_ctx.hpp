@@ -66,6 +66,7 @@ struct fos_ctx {
     unsigned long long* err_dev = nullptr;
     unsigned long long* err_host = nullptr;  // pinned host, 1 word
     fos_mc_launch defaults{};
+    bool chunk_set = false;                  // defaults.chunk fixed by fos_mc_set_launch or the tuner
 
     // optics scratch
     int* cell_of = nullptr;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -54,6 +55,24 @@ fos_status check_launch(fos_ctx* c, const fos_mc_launch& L)
     return FOS_OK;
 }
 
+// Chunk for a launch that names none while the context default was never
+// fixed: the largest power of two at most (a bound on the batch's photons) /
+// (4 x resident waves), within [256, the built-in default], so that a small
+// batch still hands every wave several claims.
+constexpr int32_t kAutoChunkMin = 256;
+constexpr int32_t kAutoChunkMax = 2048;
+
+int32_t auto_chunk(const fos_ctx* c, const fos_mc_launch& L)
+{
+    const uint64_t n = (uint64_t)std::max(c->n_items, 1);
+    const uint64_t bound = c->max_photons > UINT64_MAX / n ? UINT64_MAX : c->max_photons * n;
+    const uint64_t waves = (uint64_t)c->n_cu * (uint64_t)L.blocks_per_cu * (uint64_t)(L.block_size / 64);
+    const uint64_t per = bound / (4 * std::max<uint64_t>(waves, 1));
+    int32_t chunk = kAutoChunkMax;
+    while (chunk > kAutoChunkMin && (uint64_t)chunk > per) chunk /= 2;
+    return chunk;
+}
+
 fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
 {
     fos_mc_launch r = d;
@@ -66,6 +85,15 @@ fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
     return r;
 }
 
+
+// The launch a walk runs with: the caller's non-zero knobs over the context
+// defaults, and the per-problem chunk where neither fixes one.
+fos_mc_launch resolve(const fos_ctx* c, const fos_mc_launch* o)
+{
+    fos_mc_launch r = merge(c->defaults, o);
+    if (!(o && o->chunk) && !c->chunk_set) r.chunk = auto_chunk(c, r);
+    return r;
+}
 
 }  // namespace
 
@@ -164,6 +192,7 @@ fos_status fos_mc_set_launch(fos_ctx* c, const fos_mc_launch* L)
     fos_status s = check_launch(c, m);
     if (s != FOS_OK) return s;
     c->defaults = m;
+    if (L->chunk) c->chunk_set = true;
     return FOS_OK;
 }
 
@@ -256,7 +285,7 @@ static fos_status execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch
     if (!c->prepared) return fail(c, FOS_E_NOT_PREPARED, "no prepared problem (call fos_mc_prepare)");
     if (c->n_items == 0) return FOS_OK;
     if (!tallies) return fail(c, FOS_E_INVALID_ARG, "tallies is NULL");
-    const fos_mc_launch L = merge(c->defaults, launch);
+    const fos_mc_launch L = resolve(c, launch);
     fos_status s = check_launch(c, L);
     if (s != FOS_OK) return s;
     if (weighted && c->max_photons > (1ull << 27))
@@ -352,7 +381,7 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_m
         ms = bestv;
         return hipSuccess;
     };
-    fos_mc_launch cur = c->defaults;
+    fos_mc_launch cur = resolve(c, nullptr);
     float cur_ms = 0.f;
     e = time_one(cur, cur_ms);
     const int32_t refills[] = {4, 6, 8, 12, 16};
@@ -378,6 +407,7 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_m
     (void)hipEventDestroy(ev1);
     if (e != hipSuccess) return hip_fail(c, e, "autotune");
     c->defaults = cur;
+    c->chunk_set = true;
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
     return FOS_OK;
@@ -389,7 +419,7 @@ fos_status fos_mc_graph_capture(fos_ctx* c, const fos_mc_launch* launch, uint64_
     c->err.clear();
     if (!c->prepared) return fail(c, FOS_E_NOT_PREPARED, "no prepared problem (call fos_mc_prepare)");
     if (c->n_items > 0 && !tallies) return fail(c, FOS_E_INVALID_ARG, "tallies is NULL");
-    const fos_mc_launch L = merge(c->defaults, launch);
+    const fos_mc_launch L = resolve(c, launch);
     fos_status s = check_launch(c, L);
     if (s != FOS_OK) return s;
     DeviceGuard g(c->device);

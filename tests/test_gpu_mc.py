@@ -323,6 +323,23 @@ def test_bit_identical_across_launch_configs(ctx, torch):
     assert not (run_gpu(ctx, a, 1235) == ref).all()
 
 
+def test_per_problem_chunk_keeps_results(torch):
+    """A fresh context sizes the claim chunk per problem when no chunk is
+    given (small batches get smaller chunks); an explicit launch chunk and a
+    chunk fixed with fos_mc_set_launch are used as given.  The tallies are
+    the same bits in every case."""
+    from paper_2409_00165_amd import fos
+    a = _det_problem()
+    with fos.Context(0) as c:
+        auto = run_gpu(c.handle, a, 99)
+        assert fos.fos_mc_get_launch(c.handle).chunk == 2048
+        for chunk in (2048, 256, 3):
+            assert (run_gpu(c.handle, a, 99, launch={"chunk": chunk}) == auto).all(), chunk
+        fos.fos_mc_set_launch(c.handle, {"chunk": 512})
+        assert fos.fos_mc_get_launch(c.handle).chunk == 512
+        assert (run_gpu(c.handle, a, 99) == auto).all()
+
+
 def test_single_layer_build_matches_general_build(ctx, torch):
     """Problems whose items all have one layer run a build of the walk without
     the layer-change code.  The same items padded to three layer slots (still

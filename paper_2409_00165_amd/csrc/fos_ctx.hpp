@@ -33,6 +33,8 @@ struct fos_sur_state {
     __bf16* dlog = nullptr; float* dlog_f = nullptr;
     __bf16* dZ[2] = {}; float* dZf[2] = {};
     float* dW5pad = nullptr; float* dW1pad = nullptr; float* partial = nullptr; float* step_loss = nullptr;
+    float* splitk = nullptr;     // [4][kMaxSplits][256][256] partial weight-gradient tiles, then
+                                 // [4][kMaxSplits][256] partial bias gradients
     uint64_t* perm = nullptr;    // [epochs][4][2]
     size_t perm_cap = 0;
     // sweep scratch

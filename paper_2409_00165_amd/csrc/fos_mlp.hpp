@@ -75,6 +75,17 @@ struct GemmArgs {
     __bf16* Cb; long strideCb;             // bf16 output, leading dimension ldc
     const float* bias; long strideBias;    // BiasGelu
     const float* Z; long strideZ;          // GeluGrad: saved pre-activation, leading dimension ldc
+    // split-K (store epilogue only): K is cut into `splits` equal ranges, each
+    // workgroup writes its partial M x N tile to ws [nets][splits][M][N], and a
+    // second kernel adds the partials in split order into Cf
+    int splits = 1;
+    float* ws = nullptr;
+    // optional (TA, !TB only): the column sums of B over K for the first ncol
+    // columns (a bias gradient when B is dZ), written to
+    // csum[net * strideCsum + c]; they take the same K ranges and the same
+    // ordered reduction as the product
+    bool colsum = false; int ncol = 0;
+    float* csum = nullptr; long strideCsum = 0;
 };
 
 struct StdArgs {
@@ -144,6 +155,10 @@ hipError_t launch_spectral_reduce(int designs, int lambdas, const float* rat, co
 hipError_t launch_pack_infer(const float* params, __bf16* pk, int nets, hipStream_t st);
 hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st);
+// split-K ranges for a weight-gradient product over K rows: the largest power
+// of two up to kMaxSplits that keeps at least 8 k-steps of 32 per range
+constexpr int kMaxSplits = 16;
+int gemm_splits(int K);
 hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* mu_s, const float* mu_a,
                            const float* g, const float* n_layer, const float* thickness, const float* n_upper,
                            const float* n_lower, const float* k_lower, const float* mu0, float* x,

@@ -10,7 +10,9 @@
 //                     fp32 accumulation, 64x64x32 LDS tiles, fused epilogues
 //                     (store fp32 / bias + GELU -> fp32 Z and bf16 H /
 //                     multiply by GELU'(Z) -> fp32 and bf16 dZ); grid.z walks
-//                     the ensemble members.
+//                     the ensemble members, and for the weight gradients
+//                     (K = the batch) their split-K ranges, whose partial
+//                     tiles splitk_reduce adds in a fixed order.
 //   features        : transport problem -> the 8 raw features.
 //   standardize     : raw features -> standardised fp32 rows (+ bf16 padded
 //                     copy for the first layer's weight gradient), optional
@@ -61,7 +63,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[kBM][kBK + kPad];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[kBN][kBK + kPad];
-    const int net = blockIdx.z;
+    const int net = blockIdx.z / g.splits, split = blockIdx.z - net * g.splits;
+    const int kspan = g.K / g.splits;
     const __bf16* A = g.A + (size_t)net * g.strideA;
     const __bf16* B = g.B + (size_t)net * g.strideB;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
@@ -73,7 +76,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+    // column sums of B over the same K range (the bias gradient), by the first
+    // M tile from the B tile in LDS: lane = column, wave w the rows 8w .. 8w + 7
+    // of each k-step
+    const bool col_sums = g.colsum && blockIdx.y == 0 && n0 + lane < g.ncol;
+    float csv = 0.f;
+    for (int k0 = split * kspan; k0 < (split + 1) * kspan; k0 += kBK) {
         if (!TA) {   // A(m,k) = A[m*lda + k]
             const int r = tid >> 2, kc = (tid & 3) * 8;
             *reinterpret_cast<bf16x8*>(&As[r][kc]) =
@@ -106,10 +114,31 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (col_sums) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(&Bs[lane][wave * 8]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) csv += (float)v[e];
+        }
         __syncthreads();
     }
 
+    if (g.colsum && blockIdx.y == 0) {   // the 4 waves' column sums
+        __shared__ float csl[4][64];
+        const int c = n0 + lane;
+        csl[wave][lane] = csv;
+        __syncthreads();
+        if (wave == 0 && c < g.ncol) {
+            const float v = (csl[0][lane] + csl[1][lane]) + (csl[2][lane] + csl[3][lane]);
+            if (g.splits == 1) g.csum[(size_t)net * g.strideCsum + c] = v;
+            else g.ws[(size_t)gridDim.z * g.M * g.N + (size_t)blockIdx.z * g.N + c] = v;
+        }
+    }
     float* Cf = g.Cf ? g.Cf + (size_t)net * g.strideC : nullptr;
+    long ldc = g.ldc;
+    if (EPI == kEpiStore && g.splits > 1) {   // partial tile of this K range
+        Cf = g.ws + (size_t)blockIdx.z * g.M * g.N;
+        ldc = g.N;
+    }
     __bf16* Cb = g.Cb ? g.Cb + (size_t)net * g.strideCb : nullptr;
     const float* bias = g.bias ? g.bias + (size_t)net * g.strideBias : nullptr;
     const float* Z = g.Z ? g.Z + (size_t)net * g.strideZ : nullptr;
@@ -121,7 +150,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
                 const int col = n0 + wn + j * 16 + (lane & 15);
-                const size_t o = (size_t)row * g.ldc + col;
+                const size_t o = (size_t)row * ldc + col;
                 const float v = acc[i][j][r];
                 if (EPI == kEpiStore) {
                     Cf[o] = v;
@@ -137,16 +166,56 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             }
 }
 
+// C[net] (ldc, strideC) = sum over s = 0 .. splits-1, in that order, of the
+// partial tiles ws[net][s] (M x N, dense); likewise the column sums, whose
+// partials follow the tiles of all nets
+__global__ void splitk_reduce_kernel(const float* __restrict__ ws, int splits, int M, int N, float* C, long ldc,
+                                     long strideC, int ncol, float* csum, long strideCsum)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int net = blockIdx.y;
+    const size_t MN = (size_t)M * N;
+    if (e >= MN) return;
+    const float* p = ws + (size_t)net * splits * MN + e;
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += p[(size_t)k * MN];
+    C[(size_t)net * strideC + (e / N) * ldc + e % N] = s;
+    if (csum && e < (size_t)ncol) {
+        const float* q = ws + (size_t)gridDim.y * splits * MN + (size_t)net * splits * N + e;
+        float t = 0.0f;
+        for (int k = 0; k < splits; ++k) t += q[(size_t)k * N];
+        csum[(size_t)net * strideCsum + e] = t;
+    }
+}
+
 template <bool TA, bool TB, int EPI>
 static hipError_t launch_gemm_t(const GemmArgs& g, int nets, hipStream_t st)
 {
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), dim3(g.N / kBN, g.M / kBM, nets), dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), dim3(g.N / kBN, g.M / kBM, nets * g.splits), dim3(256), 0, st, g);
+    if (g.splits > 1) {
+        const size_t MN = (size_t)g.M * g.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256), nets), dim3(256), 0, st, g.ws,
+                           g.splits, g.M, g.N, g.Cf, g.ldc, g.strideC, g.ncol, g.colsum ? g.csum : nullptr,
+                           g.strideCsum);
+    }
     return hipGetLastError();
+}
+
+int gemm_splits(int K)
+{
+    int s = 1;
+    while (s < kMaxSplits && K % (2 * s * kBK) == 0 && K / (2 * s * kBK) >= 8) s *= 2;
+    return s;
 }
 
 hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st)
 {
     if (g.M % kBM || g.N % kBN || g.K % kBK || g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+    if (g.splits < 1 || g.splits > kMaxSplits || g.K % (g.splits * kBK) ||
+        (g.splits > 1 && (epi != kEpiStore || !g.ws || !g.Cf)))
+        return hipErrorInvalidValue;
+    if (g.colsum && (!ta || tb || !g.csum || g.ncol < 1 || g.ncol > g.N))
+        return hipErrorInvalidValue;
     if (!ta && !tb && epi == kEpiBiasGelu) return launch_gemm_t<false, false, kEpiBiasGelu>(g, nets, st);
     if (!ta && !tb && epi == kEpiStore) return launch_gemm_t<false, false, kEpiStore>(g, nets, st);
     if (!ta && tb && epi == kEpiGeluGrad) return launch_gemm_t<false, true, kEpiGeluGrad>(g, nets, st);

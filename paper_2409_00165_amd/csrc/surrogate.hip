@@ -61,7 +61,7 @@ hipError_t ensure_ws(fos_sur_state& S, int rows)
     if (S.ws_rows >= rows) return hipSuccess;
     free_ws(S);
     S.xs = nullptr; S.xb = nullptr; S.ys = nullptr; S.logits = S.probs = S.loss_rows = nullptr;
-    S.dlog = nullptr; S.dlog_f = nullptr; S.dW5pad = S.dW1pad = S.partial = S.step_loss = nullptr;
+    S.dlog = nullptr; S.dlog_f = nullptr; S.dW5pad = S.dW1pad = S.partial = S.step_loss = S.splitk = nullptr;
     for (int l = 0; l < 4; ++l) { S.Z[l] = nullptr; S.H[l] = nullptr; }
     for (int i = 0; i < 2; ++i) { S.dZ[i] = nullptr; S.dZf[i] = nullptr; }
     const size_t R = (size_t)fos::kNets * rows;
@@ -89,6 +89,7 @@ hipError_t ensure_ws(fos_sur_state& S, int rows)
     A(&S.dW1pad, (size_t)fos::kNets * fos::kPadIn * fos::kHidden * sizeof(float));
     A(&S.partial, (size_t)fos::kNets * kColsumChunks * fos::kHidden * sizeof(float));
     A(&S.step_loss, fos::kNets * sizeof(float));
+    A(&S.splitk, (size_t)fos::kNets * fos::kMaxSplits * (fos::kHidden + 1) * fos::kHidden * sizeof(float));
     if (e == hipSuccess) S.ws_rows = rows;
     return e;
 }
@@ -132,23 +133,29 @@ hipError_t forward(fos_sur_state& S, int rows_pad, hipStream_t st)
     return fos::launch_gemm(g, false, false, fos::kEpiStore, fos::kNets, st);
 }
 
-// Backward pass after a training forward + softmax_ce: fills S.grads.
+// Backward pass after a training forward + softmax_ce: fills S.grads.  The
+// weight gradients reduce over the batch rows, so they run split-K.
 hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
 {
     const int R = rows;                       // rows_pad == rows in training
     const long RH = (long)R * fos::kHidden;
     const long PS = (long)fos::kParams, BS = (long)fos::kBfParams;
+    const int splits = fos::gemm_splits(R);
+    // split-K weight gradient, with the bias gradient (the column sums of the
+    // same bf16 dZ operand) folded into the product
+    auto split_k = [&](fos::GemmArgs& a, int ncol, float* bias_grad) {
+        a.splits = splits; a.ws = S.splitk;
+        a.colsum = true; a.ncol = ncol; a.csum = bias_grad; a.strideCsum = PS;
+    };
     hipError_t e;
     // dW5 = H4^T dlog (padded), db5 = colsum(dlog)
     fos::GemmArgs g = gemm(fos::kHidden, fos::kPadOut, R, S.H[3], fos::kHidden, RH, S.dlog, fos::kPadOut,
                            (long)R * fos::kPadOut, S.dW5pad, fos::kPadOut, (long)fos::kHidden * fos::kPadOut,
                            nullptr, 0, nullptr, 0, nullptr, 0);
+    split_k(g, 3, S.grads + fos::kOffB5);
     if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
     if ((e = fos::launch_copy_block(S.dW5pad, fos::kPadOut, (size_t)fos::kHidden * fos::kPadOut, fos::kHidden, 3,
                                     S.grads + fos::kOffW5, fos::kParams, fos::kNets, st)) != hipSuccess)
-        return e;
-    if ((e = fos::launch_colsum(S.dlog_f, R, 3, (size_t)R * 3, S.partial, kColsumChunks, S.grads + fos::kOffB5,
-                                fos::kParams, fos::kNets, st)) != hipSuccess)
         return e;
     // dZ4 = (dlog W5^T) * gelu'(Z4)
     g = gemm(R, fos::kHidden, fos::kPadK5, S.dlog, fos::kPadOut, (long)R * fos::kPadOut, S.wb + fos::kBfW5t,
@@ -163,10 +170,8 @@ hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
         const int hl = 2 - s;                 // H index of the layer input: H3, H2, H1
         g = gemm(fos::kHidden, fos::kHidden, R, S.H[hl], fos::kHidden, RH, S.dZ[cur], fos::kHidden, RH,
                  S.grads + wof[s], fos::kHidden, PS, nullptr, 0, nullptr, 0, nullptr, 0);
+        split_k(g, fos::kHidden, S.grads + bof[s]);
         if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
-        if ((e = fos::launch_colsum(S.dZf[cur], R, fos::kHidden, (size_t)RH, S.partial, kColsumChunks,
-                                    S.grads + bof[s], fos::kParams, fos::kNets, st)) != hipSuccess)
-            return e;
         g = gemm(R, fos::kHidden, fos::kHidden, S.dZ[cur], fos::kHidden, RH, S.wb + wbf[s], fos::kHidden, BS,
                  S.dZf[cur ^ 1], fos::kHidden, RH, S.dZ[cur ^ 1], RH, nullptr, 0, S.Z[hl], RH);
         if ((e = fos::launch_gemm(g, false, true, fos::kEpiGeluGrad, fos::kNets, st)) != hipSuccess) return e;
@@ -175,13 +180,10 @@ hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
     // layer 1: dW1 = X^T dZ1 (inputs padded to 64), db1 = colsum(dZ1)
     g = gemm(fos::kPadIn, fos::kHidden, R, S.xb, fos::kPadIn, (long)R * fos::kPadIn, S.dZ[cur], fos::kHidden, RH,
              S.dW1pad, fos::kHidden, (long)fos::kPadIn * fos::kHidden, nullptr, 0, nullptr, 0, nullptr, 0);
+    split_k(g, fos::kHidden, S.grads + fos::kOffB1);
     if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
-    if ((e = fos::launch_copy_block(S.dW1pad, fos::kHidden, (size_t)fos::kPadIn * fos::kHidden, fos::kFeatures,
-                                    fos::kHidden, S.grads + fos::kOffW1, fos::kParams, fos::kNets, st)) !=
-        hipSuccess)
-        return e;
-    return fos::launch_colsum(S.dZf[cur], R, fos::kHidden, (size_t)RH, S.partial, kColsumChunks,
-                              S.grads + fos::kOffB1, fos::kParams, fos::kNets, st);
+    return fos::launch_copy_block(S.dW1pad, fos::kHidden, (size_t)fos::kPadIn * fos::kHidden, fos::kFeatures,
+                                  fos::kHidden, S.grads + fos::kOffW1, fos::kParams, fos::kNets, st);
 }
 
 hipError_t softmax(fos_sur_state& S, int rows, int rows_pad, bool targets, hipStream_t st)

@@ -20,7 +20,8 @@
 //   first_layer     : the 8-wide input layer on the VALU (fp32).
 //   softmax_ce      : softmax of the 3 logits, cross-entropy against the Monte
 //                     Carlo fractions, d loss / d logits = (p - y) / B.
-//   colsum          : bias gradients (two-stage, deterministic).
+//   colsum          : column sums, two-stage and deterministic (the per-step
+//                     loss; bias gradients come with the split-K products).
 //   adam            : Adam on fp32 master weights, refreshing bf16 copies.
 // Prediction (network + ensemble gate) is one fused kernel in mlp_infer.hip.
 #include <hip/hip_runtime.h>

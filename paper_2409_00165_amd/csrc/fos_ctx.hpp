@@ -30,9 +30,9 @@ struct fos_sur_state {
     float* xs = nullptr; __bf16* xb = nullptr; float* ys = nullptr;
     float* Z[4] = {}; __bf16* H[4] = {};
     float* logits = nullptr; float* probs = nullptr; float* loss_rows = nullptr;
-    __bf16* dlog = nullptr; float* dlog_f = nullptr;
-    __bf16* dZ[2] = {}; float* dZf[2] = {};
-    float* dW5pad = nullptr; float* dW1pad = nullptr; float* partial = nullptr; float* step_loss = nullptr;
+    __bf16* dlog = nullptr;
+    __bf16* dZ[2] = {};
+    float* dW5pad = nullptr; float* dW1pad = nullptr;
     float* splitk = nullptr;     // [4][kMaxSplits][256][256] partial weight-gradient tiles, then
                                  // [4][kMaxSplits][256] partial bias gradients
     uint64_t* perm = nullptr;    // [epochs][4][2]

@@ -110,7 +110,6 @@ struct SoftmaxArgs {
     const float* ys;           // targets or null (inference)
     float* loss_rows;          // [nets][rows_pad]
     __bf16* dlog;              // [nets][rows_pad][64]
-    float* dlog_f;             // [nets][rows_pad][3]
     float inv_batch;
 };
 
@@ -167,13 +166,13 @@ hipError_t launch_standardize(const StdArgs& a, int nets, hipStream_t st);
 hipError_t launch_first_layer(int rows_pad, const float* xs, const float* params, size_t pstride, float* Z1,
                               __bf16* H1, int nets, hipStream_t st);
 hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st);
-hipError_t launch_colsum(const float* src, int rows, int cols, size_t sstride, float* partial, int chunks,
-                         float* out, size_t ostride, int nets, hipStream_t st);
 hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
                              size_t dstride, int nets, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st);
 hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t st);
 hipError_t launch_feature_stats(const float* x, int64_t n, float* stats, hipStream_t st);
-hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st);
+// dst[m] = (add ? dst[m] : 0) + scale * (sum of member m's per-row losses [nets][rows])
+hipError_t launch_loss_sum(const float* loss_rows, int rows, float* dst, float scale, bool add, int nets,
+                           hipStream_t st);
 
 }  // namespace fos

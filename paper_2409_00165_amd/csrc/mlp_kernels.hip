@@ -20,8 +20,7 @@
 //   first_layer     : the 8-wide input layer on the VALU (fp32).
 //   softmax_ce      : softmax of the 3 logits, cross-entropy against the Monte
 //                     Carlo fractions, d loss / d logits = (p - y) / B.
-//   colsum          : column sums, two-stage and deterministic (the per-step
-//                     loss; bias gradients come with the split-K products).
+//   loss_sum        : the per-member loss of a batch (deterministic tree).
 //   adam            : Adam on fp32 master weights, refreshing bf16 copies.
 // Prediction (network + ensemble gate) is one fused kernel in mlp_infer.hip.
 #include <hip/hip_runtime.h>
@@ -299,7 +298,7 @@ __global__ void first_layer_kernel(int rows_pad, const float* xs, const float* p
 
 // softmax over the 3 logits (columns 0..2 of a 64-wide fp32 row) + b5;
 // with targets: per-row loss into loss_rows, dlogits (p - y)/B into a 64-wide
-// bf16 row (zeros beyond 3) and fp32 [rows][3]
+// bf16 row (zeros beyond 3)
 __global__ void softmax_ce_kernel(SoftmaxArgs a)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,40 +324,9 @@ __global__ void softmax_ce_kernel(SoftmaxArgs a)
         for (int c = 0; c < 3; ++c) loss -= y[c] * (l[c] - ls);
         a.loss_rows[(size_t)m * a.rows_pad + r] = valid ? loss : 0.f;
         __bf16* d = a.dlog + ((size_t)m * a.rows_pad + r) * kPadOut;
-        float* df = a.dlog_f + ((size_t)m * a.rows_pad + r) * 3;
-        for (int c = 0; c < 3; ++c) {
-            const float v = valid ? (p[c] - y[c]) * a.inv_batch : 0.f;
-            d[c] = (__bf16)v;
-            df[c] = v;
-        }
+        for (int c = 0; c < 3; ++c) d[c] = (__bf16)(valid ? (p[c] - y[c]) * a.inv_batch : 0.f);
         for (int c = 3; c < kPadOut; ++c) d[c] = (__bf16)0.0f;
     }
-}
-
-// column sums of a [rows][cols] fp32 matrix per member, deterministic two
-// stages: partial[m][chunk][col] then out[m][col] (+= offset into grads)
-__global__ void colsum_partial_kernel(const float* src, int rows, int cols, size_t sstride, int chunk_rows,
-                                      float* partial)
-{
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ch = blockIdx.y, m = blockIdx.z;
-    if (col >= cols) return;
-    const float* s = src + (size_t)m * sstride;
-    const int r0 = ch * chunk_rows;
-    const int r1 = r0 + chunk_rows < rows ? r0 + chunk_rows : rows;
-    float acc = 0.f;
-    for (int r = r0; r < r1; ++r) acc += s[(size_t)r * cols + col];
-    partial[((size_t)m * gridDim.y + ch) * cols + col] = acc;
-}
-
-__global__ void colsum_final_kernel(const float* partial, int chunks, int cols, float* out, size_t ostride)
-{
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y;
-    if (col >= cols) return;
-    float acc = 0.f;
-    for (int c = 0; c < chunks; ++c) acc += partial[((size_t)m * chunks + c) * cols + col];
-    out[(size_t)m * ostride + col] = acc;
 }
 
 // copy a [rows][cols] sub-block of a padded fp32 matrix into the flat gradient
@@ -419,10 +387,23 @@ __global__ void refresh_bf16_kernel(const float* w, __bf16* wb)
     wb[(size_t)m * kBfParams + j] = (__bf16)v;
 }
 
-__global__ void accumulate_kernel(const float* src, float* dst, int n, float scale)
+// dst[m] (+)= scale * sum of member m's `rows` per-row losses, one block of 256
+// per member: strided partial sums, then a fixed tree (deterministic)
+__global__ __launch_bounds__(256) void loss_sum_kernel(const float* __restrict__ loss_rows, int rows, float* dst,
+                                                       float scale, int add)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] += scale * src[i];
+    __shared__ float part[256];
+    const int m = blockIdx.x, t = threadIdx.x;
+    const float* l = loss_rows + (size_t)m * rows;
+    float s = 0.f;
+    for (int r = t; r < rows; r += 256) s += l[r];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) part[t] += part[t + o];
+        __syncthreads();
+    }
+    if (t == 0) dst[m] = (add ? dst[m] : 0.f) + scale * part[0];
 }
 
 // member mean, spread = max_c (max_m p - min_m p), domain test of the raw
@@ -662,19 +643,6 @@ hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* src, int rows, int cols, size_t sstride, float* partial, int chunks,
-                         float* out, size_t ostride, int nets, hipStream_t st)
-{
-    const int chunk_rows = (rows + chunks - 1) / chunks;
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((cols + 63) / 64, chunks, nets), dim3(64), 0, st, src, rows,
-                       cols, sstride, chunk_rows, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 63) / 64, nets), dim3(64), 0, st, partial, chunks, cols,
-                       out, ostride);
-    return hipGetLastError();
-}
-
 hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
                              size_t dstride, int nets, hipStream_t st)
 {
@@ -695,9 +663,10 @@ hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate(const float* src, float* dst, int n, float scale, hipStream_t st)
+hipError_t launch_loss_sum(const float* loss_rows, int rows, float* dst, float scale, bool add, int nets,
+                           hipStream_t st)
 {
-    hipLaunchKernelGGL(accumulate_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n, scale);
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(nets), dim3(256), 0, st, loss_rows, rows, dst, scale, add ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -19,7 +19,6 @@ using fosrt::hip_fail;
 
 namespace {
 
-constexpr int kColsumChunks = 64;
 
 hipError_t alloc_ws(fos_sur_state& S, void** p, size_t bytes)
 {
@@ -61,9 +60,9 @@ hipError_t ensure_ws(fos_sur_state& S, int rows)
     if (S.ws_rows >= rows) return hipSuccess;
     free_ws(S);
     S.xs = nullptr; S.xb = nullptr; S.ys = nullptr; S.logits = S.probs = S.loss_rows = nullptr;
-    S.dlog = nullptr; S.dlog_f = nullptr; S.dW5pad = S.dW1pad = S.partial = S.step_loss = S.splitk = nullptr;
+    S.dlog = nullptr; S.dW5pad = S.dW1pad = S.splitk = nullptr;
     for (int l = 0; l < 4; ++l) { S.Z[l] = nullptr; S.H[l] = nullptr; }
-    for (int i = 0; i < 2; ++i) { S.dZ[i] = nullptr; S.dZf[i] = nullptr; }
+    for (int i = 0; i < 2; ++i) S.dZ[i] = nullptr;
     const size_t R = (size_t)fos::kNets * rows;
     hipError_t e = hipSuccess;
     auto A = [&](void* pp, size_t bytes) {
@@ -76,19 +75,15 @@ hipError_t ensure_ws(fos_sur_state& S, int rows)
     A(&S.probs, R * 3 * sizeof(float));
     A(&S.loss_rows, R * sizeof(float));
     A(&S.dlog, R * fos::kPadOut * sizeof(__bf16));
-    A(&S.dlog_f, R * 3 * sizeof(float));
     for (int l = 0; l < 4; ++l) {
         A(&S.Z[l], R * fos::kHidden * sizeof(float));
         A(&S.H[l], R * fos::kHidden * sizeof(__bf16));
     }
     for (int i = 0; i < 2; ++i) {
         A(&S.dZ[i], R * fos::kHidden * sizeof(__bf16));
-        A(&S.dZf[i], R * fos::kHidden * sizeof(float));
     }
     A(&S.dW5pad, (size_t)fos::kNets * fos::kHidden * fos::kPadOut * sizeof(float));
     A(&S.dW1pad, (size_t)fos::kNets * fos::kPadIn * fos::kHidden * sizeof(float));
-    A(&S.partial, (size_t)fos::kNets * kColsumChunks * fos::kHidden * sizeof(float));
-    A(&S.step_loss, fos::kNets * sizeof(float));
     A(&S.splitk, (size_t)fos::kNets * fos::kMaxSplits * (fos::kHidden + 1) * fos::kHidden * sizeof(float));
     if (e == hipSuccess) S.ws_rows = rows;
     return e;
@@ -159,7 +154,7 @@ hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
         return e;
     // dZ4 = (dlog W5^T) * gelu'(Z4)
     g = gemm(R, fos::kHidden, fos::kPadK5, S.dlog, fos::kPadOut, (long)R * fos::kPadOut, S.wb + fos::kBfW5t,
-             fos::kPadK5, BS, S.dZf[0], fos::kHidden, RH, S.dZ[0], RH, nullptr, 0, S.Z[3], RH);
+             fos::kPadK5, BS, nullptr, fos::kHidden, RH, S.dZ[0], RH, nullptr, 0, S.Z[3], RH);
     if ((e = fos::launch_gemm(g, false, true, fos::kEpiGeluGrad, fos::kNets, st)) != hipSuccess) return e;
     // layers 4, 3, 2: dW = H_{l-1}^T dZ_l, db = colsum(dZ_l), dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
     const size_t wof[3] = {fos::kOffW4, fos::kOffW3, fos::kOffW2};
@@ -173,7 +168,7 @@ hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
         split_k(g, fos::kHidden, S.grads + bof[s]);
         if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
         g = gemm(R, fos::kHidden, fos::kHidden, S.dZ[cur], fos::kHidden, RH, S.wb + wbf[s], fos::kHidden, BS,
-                 S.dZf[cur ^ 1], fos::kHidden, RH, S.dZ[cur ^ 1], RH, nullptr, 0, S.Z[hl], RH);
+                 nullptr, fos::kHidden, RH, S.dZ[cur ^ 1], RH, nullptr, 0, S.Z[hl], RH);
         if ((e = fos::launch_gemm(g, false, true, fos::kEpiGeluGrad, fos::kNets, st)) != hipSuccess) return e;
         cur ^= 1;
     }
@@ -193,7 +188,7 @@ hipError_t softmax(fos_sur_state& S, int rows, int rows_pad, bool targets, hipSt
     a.params = S.params; a.pstride = fos::kParams;
     a.logits = S.logits; a.probs = S.probs;
     a.ys = targets ? S.ys : nullptr;
-    a.loss_rows = S.loss_rows; a.dlog = S.dlog; a.dlog_f = S.dlog_f;
+    a.loss_rows = S.loss_rows; a.dlog = S.dlog;
     a.inv_batch = 1.0f / (float)rows;
     return fos::launch_softmax_ce(a, fos::kNets, st);
 }
@@ -341,13 +336,11 @@ fos_status fos_sur_train(fos_ctx* c, const float* x, const float* y, int64_t n, 
                              (float)(1.0 / (1.0 - std::pow(0.9, (double)S.adam_step))),
                              (float)(1.0 / (1.0 - std::pow(0.999, (double)S.adam_step)))};
             if ((e = fos::launch_adam(aa, fos::kNets, st)) != hipSuccess) return hip_fail(c, e, "adam");
-            if (o->loss_history) {
-                if ((e = fos::launch_colsum(S.loss_rows, B, 1, (size_t)B, S.partial, kColsumChunks, S.step_loss, 1,
-                                            fos::kNets, st)) != hipSuccess ||
-                    (e = fos::launch_accumulate(S.step_loss, o->loss_history + (size_t)ep * fos::kNets, fos::kNets,
-                                                (float)(1.0 / ((double)B * steps_per_epoch)), st)) != hipSuccess)
-                    return hip_fail(c, e, "loss history");
-            }
+            if (o->loss_history &&
+                (e = fos::launch_loss_sum(S.loss_rows, B, o->loss_history + (size_t)ep * fos::kNets,
+                                          (float)(1.0 / ((double)B * steps_per_epoch)), true, fos::kNets, st)) !=
+                    hipSuccess)
+                return hip_fail(c, e, "loss history");
         }
     }
     // host copy of the stats for save()
@@ -403,13 +396,8 @@ fos_status fos_sur_grad(fos_ctx* c, const float* x, const float* y, int64_t n, f
     if ((e = hipMemcpyAsync(grads, S.grads, (size_t)fos::kNets * fos::kParams * sizeof(float),
                             hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hip_fail(c, e, "gradient copy");
-    if (loss) {
-        if ((e = fos::launch_colsum(S.loss_rows, R, 1, (size_t)R, S.partial, kColsumChunks, S.step_loss, 1, fos::kNets,
-                                    st)) != hipSuccess ||
-            (e = hipMemsetAsync(loss, 0, fos::kNets * sizeof(float), st)) != hipSuccess ||
-            (e = fos::launch_accumulate(S.step_loss, loss, fos::kNets, 1.0f / (float)R, st)) != hipSuccess)
-            return hip_fail(c, e, "loss");
-    }
+    if (loss && (e = fos::launch_loss_sum(S.loss_rows, R, loss, 1.0f / (float)R, false, fos::kNets, st)) != hipSuccess)
+        return hip_fail(c, e, "loss");
     return FOS_OK;
 }
 

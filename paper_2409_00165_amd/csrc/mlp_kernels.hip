@@ -81,28 +81,38 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     // of each k-step
     const bool col_sums = g.colsum && blockIdx.y == 0 && n0 + lane < g.ncol;
     float csv = 0.f;
-    for (int k0 = split * kspan; k0 < (split + 1) * kspan; k0 += kBK) {
+    // the next k-step's tiles are loaded into registers while this one
+    // multiplies (one register set, written to LDS after the barrier)
+    const int kbeg = split * kspan, kend = kbeg + kspan;
+    auto load_a = [&](int k0) -> bf16x8 {
+        if (!TA) return *reinterpret_cast<const bf16x8*>(A + (size_t)(m0 + (tid >> 2)) * g.lda + k0 + (tid & 3) * 8);
+        return *reinterpret_cast<const bf16x8*>(A + (size_t)(k0 + (tid >> 3)) * g.lda + m0 + (tid & 7) * 8);
+    };
+    auto load_b = [&](int k0) -> bf16x8 {
+        if (TB) return *reinterpret_cast<const bf16x8*>(B + (size_t)(n0 + (tid >> 2)) * g.ldb + k0 + (tid & 3) * 8);
+        return *reinterpret_cast<const bf16x8*>(B + (size_t)(k0 + (tid >> 3)) * g.ldb + n0 + (tid & 7) * 8);
+    };
+    bf16x8 va = load_a(kbeg), vb = load_b(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         if (!TA) {   // A(m,k) = A[m*lda + k]
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            *reinterpret_cast<bf16x8*>(&As[r][kc]) =
-                *reinterpret_cast<const bf16x8*>(A + (size_t)(m0 + r) * g.lda + k0 + kc);
+            *reinterpret_cast<bf16x8*>(&As[tid >> 2][(tid & 3) * 8]) = va;
         } else {     // A(m,k) = A[k*lda + m]
             const int kk = tid >> 3, mc = (tid & 7) * 8;
-            const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + (size_t)(k0 + kk) * g.lda + m0 + mc);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) As[mc + j][kk] = v[j];
+            for (int j = 0; j < 8; ++j) As[mc + j][kk] = va[j];
         }
         if (TB) {    // B(k,n) = B[n*ldb + k]
-            const int r = tid >> 2, kc = (tid & 3) * 8;
-            *reinterpret_cast<bf16x8*>(&Bs[r][kc]) =
-                *reinterpret_cast<const bf16x8*>(B + (size_t)(n0 + r) * g.ldb + k0 + kc);
+            *reinterpret_cast<bf16x8*>(&Bs[tid >> 2][(tid & 3) * 8]) = vb;
         } else {     // B(k,n) = B[k*ldb + n]
             const int kk = tid >> 3, nc = (tid & 7) * 8;
-            const bf16x8 v = *reinterpret_cast<const bf16x8*>(B + (size_t)(k0 + kk) * g.ldb + n0 + nc);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Bs[nc + j][kk] = v[j];
+            for (int j = 0; j < 8; ++j) Bs[nc + j][kk] = vb[j];
         }
         __syncthreads();
+        if (k0 + kBK < kend) {
+            va = load_a(k0 + kBK);
+            vb = load_b(k0 + kBK);
+        }
         bf16x8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)

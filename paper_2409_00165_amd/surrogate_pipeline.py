@@ -116,30 +116,56 @@ def training_recipe_id(seed: int) -> str:
     return h.hexdigest()[:16]
 
 
+def _walk_cost(a):
+    """Ordering key for the labelling walks of single-layer items: the length
+    of their longest walks, about the diffusion time (tau_s (1 - g))^2 of the
+    slab, or the scatterings before absorption (tau_s / tau_a) if fewer."""
+    t = a["thickness"][:, 0]
+    tau_s, tau_a = a["mu_s"][:, 0] * t, a["mu_a"][:, 0] * t
+    red = tau_s * (1.0 - a["g"][:, 0])
+    return np.minimum(tau_s / np.maximum(tau_a, 1e-12), np.maximum(red, 1.0) ** 2)
+
+
 def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True):
     """n single-layer items labelled by the walk at `photons` each.
     Returns (x [n*8], y [n*3], photon-steps, seconds).  With label=False only
     the features are made (y is None): the items are a function of
-    (n, seed, chunk), so stored labels can be re-joined to their features."""
+    (n, seed, chunk), so stored labels can be re-joined to their features.
+
+    The walks take the items in launches of `chunk`, ordered by _walk_cost,
+    longest first.  A few photons of the thick, weakly absorbing items walk
+    10^7..10^8 steps on one lane and a launch lasts as long as its longest
+    photon: gathered in the first launch they run side by side, and the
+    launches after it hold short walks only.  Labels depend on
+    (n, seed, chunk)."""
     import torch
-    xs, ys = [], []
-    steps = 0
     t0 = time.perf_counter()
+    parts, xs = [], []
     for c, b in enumerate(range(0, n, chunk)):
         m = min(chunk, n - b)
         arrays = W.surrogate_training_items(m, seed + 7919 * c, photons=photons)
-        prob = device_problem(arrays)
         x = torch.zeros(m * fos.SUR_FEATURES, dtype=torch.float32, device="cuda")
-        fos.fos_sur_features(ctx, prob, x)
+        fos.fos_sur_features(ctx, device_problem(arrays), x)
         xs.append(x)
-        if label:
-            rat, s = mc_fractions(ctx, prob, seed + c)
-            ys.append(rat)
-            steps += s
-            if log:
-                log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
+        parts.append(arrays)
+    x = torch.cat(xs)
+    if not label:
+        torch.cuda.synchronize()
+        return x, None, 0, time.perf_counter() - t0
+    items = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    order = np.argsort(-_walk_cost(items), kind="stable")
+    y = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
+    steps = 0
+    for c, b in enumerate(range(0, n, chunk)):
+        idx = order[b:b + chunk]
+        m = len(idx)
+        rat, s = mc_fractions(ctx, device_problem({k: v[idx] for k, v in items.items()}), seed + c)
+        y.view(n, 3)[torch.from_numpy(idx).cuda()] = rat.view(m, 3)
+        steps += s
+        if log:
+            log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
     torch.cuda.synchronize()
-    return torch.cat(xs), (torch.cat(ys) if label else None), steps, time.perf_counter() - t0
+    return x, y, steps, time.perf_counter() - t0
 
 
 def train(ctx, x, y, epochs=30, batch=8192, lr=1e-3, lr_min=1e-5, seed=1):

@@ -145,3 +145,34 @@ def test_trained_surrogate_tracks_monte_carlo(trained, torch):
     e = SP.errors(rat.cpu().numpy(), y.cpu().numpy())
     print("held-out error vs MC (small model):", e, "in-domain", float(ind.float().mean()), flush=True)
     assert e["mean"] < 0.05
+
+
+def test_training_labels_follow_their_items_across_launches(torch):
+    """make_training_set walks the items longest first, in several launches,
+    and puts each label back on its item.  Each item is walked once more on
+    its own seed, in recipe order: the two estimates agree within 5 binomial
+    standard errors item by item (a label on the wrong item would be far off),
+    and the features are those of label=False."""
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    from paper_2409_00165_amd import workloads as W
+    c = fos.Context(0)
+    h = c.handle
+    n, ph, chunk = 3000, 2000, 1000
+    x, y, steps, _ = SP.make_training_set(h, n, ph, seed=77, chunk=chunk)
+    x2, _, _, _ = SP.make_training_set(h, n, ph, seed=77, chunk=chunk, label=False)
+    assert torch.equal(x, x2) and steps > 0
+    parts = [W.surrogate_training_items(min(chunk, n - b), 77 + 7919 * k, photons=ph)
+             for k, b in enumerate(range(0, n, chunk))]
+    items = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
+    again, _ = SP.mc_fractions(h, SP.device_problem(items), 4242)
+    torch.cuda.synchronize()
+    a = y.view(n, 3).cpu().numpy().astype(np.float64)
+    b = again.view(n, 3).cpu().numpy().astype(np.float64)
+    p = 0.5 * (a + b)
+    se = np.sqrt(np.maximum(p * (1 - p), 1.0 / ph) * 2.0 / ph)
+    z = np.abs(a - b) / se
+    print("labels vs a second walk of the same items: worst z", z.max(), flush=True)
+    assert (z <= 5.0).all()
+    assert np.abs(a - b).mean() < 0.01
+    c.close()

@@ -1,0 +1,30 @@
+"""Host logic of the surrogate pipeline that needs no GPU: the ordering key
+of the labelling walks (the length of an item's longest walks)."""
+import numpy as np
+
+from paper_2409_00165_amd import surrogate_pipeline as SP
+from paper_2409_00165_amd import workloads as W
+
+
+def _items(tau_s, tau_a, g, t=100.0):
+    n = len(tau_s)
+    return {"thickness": np.full((n, 1), t), "mu_s": (np.asarray(tau_s, float) / t)[:, None],
+            "mu_a": (np.asarray(tau_a, float) / t)[:, None], "g": np.asarray(g, float)[:, None]}
+
+
+def test_walk_cost_is_diffusion_time_or_scatterings_before_absorption():
+    # thick and lossless: (tau_s (1 - g))^2; strongly absorbing: tau_s / tau_a; thin: at least 1
+    c = SP._walk_cost(_items([1e4, 1e4, 1e4, 0.1], [1e-4, 10.0, 1e-4, 1e-4], [0.0, 0.0, 0.9, 0.0]))
+    assert np.allclose(c, [1e8, 1e3, 1e6, 1.0])
+
+
+def test_walk_cost_orders_the_training_recipe_longest_first():
+    a = W.surrogate_training_items(20000, 5)
+    c = SP._walk_cost(a)
+    order = np.argsort(-c, kind="stable")
+    t = a["thickness"][:, 0]
+    tau_red = a["mu_s"][:, 0] * t * (1 - a["g"][:, 0])
+    # the first percent of the order holds the thickest reduced depths of the recipe
+    head = order[: len(order) // 100]
+    assert np.median(tau_red[head]) > np.quantile(tau_red, 0.9)
+    assert np.all(np.isfinite(c)) and np.all(c >= 0)

@@ -11,7 +11,11 @@ This module only marshals arguments through ctypes.
 Parity status (each function's pins live in ``tests/test_oracle_*.py``):
   philox, fresnel, hg_cos, walk, walk_batch, mie_coeffs, mie_sphere,
   layer_optics, optics_batch -- pinned (published test vectors, closed forms,
-  limits, invariants, independent special-function evaluation).
+  limits, invariants, independent special-function evaluation; the asymmetry
+  parameter by quadrature of the phase function, the mixture rules by
+  contrast-free and index-matched populations).  One factor is pinned by
+  continuity only: the absorbing-host factor exp(-alpha)/gamma of the
+  scattering cross section (eqs. (10), (12)), which reduces to 1 as k_m -> 0.
 """
 from __future__ import annotations
 

@@ -13,7 +13,10 @@ gradient with respect to the logits is (p - y) / B.  Optimiser: Adam.
 
 Parity status: forward pinned by a pure-Python loop evaluation on a tiny
 network; backward pinned by central finite differences; Adam pinned by its
-first-step property (each weight moves by lr * sign(gradient)).
+first-step property (each weight moves by lr * sign(gradient)), by the
+constant-gradient property at every later step (the bias-corrected moments
+are exactly g and g^2, so each step is lr g / (|g| + eps)) and by the closed
+form of the moments under an alternating gradient.
 """
 from __future__ import annotations
 

@@ -93,6 +93,46 @@ def test_adam_first_step_moves_by_lr_times_sign():
         assert np.allclose(b1 - b0, -1e-3 * np.sign(gb), rtol=1e-6)
 
 
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    # with a gradient that never changes, the bias-corrected moments are
+    # exactly g and g^2 at every step t, so each step moves every weight by
+    # lr g / (|g| + eps) -- steps 2..10 fail without the (1 - beta^t)
+    # corrections or with a correction that does not follow t
+    params = mlp.init(2, sizes=(8, 4, 3))
+    rng = np.random.default_rng(5)
+    grads = [(rng.choice([-1.0, 1.0], size=W.shape) * rng.uniform(0.01, 3.0, size=W.shape),
+              rng.uniform(-2.0, 2.0, size=b.shape)) for W, b in params]
+    eps = 1e-8
+    opt = mlp.Adam(params, lr=2e-3, eps=eps)
+    cur = params
+    for t in range(1, 11):
+        lr = 2e-3 * (1.0 - 0.05 * t)       # a schedule changes only the step size
+        new = opt.step(cur, grads, lr=lr)
+        for (W0, b0), (W1, b1), (gW, gb) in zip(cur, new, grads):
+            assert np.allclose(W1 - W0, -lr * gW / (np.abs(gW) + eps), rtol=1e-9, atol=0)
+            assert np.allclose(b1 - b0, -lr * gb / (np.abs(gb) + eps), rtol=1e-9, atol=0)
+        cur = new
+
+
+def test_adam_alternating_gradient_closed_form():
+    # gradients g, -g, g, -g, ...: the first moment is the geometric sum
+    # m_t = (1 - b1) g (-1)^(t-1) (1 - (-b1)^t) / (1 + b1) and the second
+    # v_t = (1 - b2^t) g^2, so the step of iteration t is
+    # lr m_t / (1 - b1^t) / (sqrt(v_t / (1 - b2^t)) + eps)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-3
+    params = mlp.init(4, sizes=(8, 3))
+    g = np.random.default_rng(6).normal(size=params[0][0].shape)
+    opt = mlp.Adam(params, lr=lr, b1=b1, b2=b2, eps=eps)
+    cur = params
+    for t in range(1, 13):
+        s = (-1.0) ** (t - 1)
+        new = opt.step(cur, [(s * g, np.zeros_like(params[0][1]))])
+        m = (1 - b1) * g * s * (1 - (-b1) ** t) / (1 + b1)
+        step = lr * (m / (1 - b1**t)) / (np.abs(g) + eps)
+        assert np.allclose(new[0][0] - cur[0][0], -step, rtol=1e-9, atol=1e-18)
+        cur = new
+
+
 def test_training_reduces_loss_on_a_smooth_target():
     rng = np.random.default_rng(4)
     x = rng.normal(size=(256, 8))

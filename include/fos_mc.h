@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define FOS_ABI_VERSION 2
+#define FOS_ABI_VERSION 3
 #define FOS_MAX_LAYERS 8
 
 /* tally slots per item, in this order, uint64 each */
@@ -127,6 +127,12 @@ typedef struct {
     int32_t chunk;          /* photons a wave claims from the queue at once      */
     int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu             */
     uint64_t max_steps;     /* per-photon step cap (photons beyond it -> CAPPED) */
+    int32_t tail_lanes;     /* > 0: a wave with no photons left to claim and at
+                               most this many in flight computes their next
+                               random draws on all 64 lanes ahead of the steps
+                               that use them (a build of the walk with that
+                               phase); -1: the build without it; 1..64, -1     */
+    int32_t reserved;       /* must be 0                                          */
 } fos_mc_launch;
 
 /* Validate `problem` and pack it into the context's device item table

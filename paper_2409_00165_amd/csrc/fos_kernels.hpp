@@ -44,6 +44,9 @@ struct WalkArgs {
     uint32_t max_steps;
     int chunk;
     int refill_min;
+    int tail_lanes;               // > 0: the build of the walk with the tail phase; a wave with no
+                                  // chunk left and at most this many photons in flight prepares
+                                  // their draws on all its lanes (0 = the build without it)
 };
 
 enum OptErrCode : int {
@@ -125,7 +128,7 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, h
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted = false);
 hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st);
 hipError_t launch_weighted_fractions(int n, const unsigned long long* tallies, float* rat, float* se, hipStream_t st);
-size_t walk_lds_bytes(int block_size, int max_layers, bool weighted = false);
+size_t walk_lds_bytes(int block_size, int max_layers, bool weighted = false, bool tail = false);
 hipError_t launch_philox_words(int n, const uint64_t* photon, const uint32_t* step, const uint32_t* stream,
                                uint64_t seed, uint32_t* out, hipStream_t st);
 hipError_t launch_eval_fresnel(int n, const float* c, const float* ni, const float* nt, const float* kt,

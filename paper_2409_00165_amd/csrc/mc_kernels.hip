@@ -214,8 +214,94 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
 // SINGLE is for problems whose items all have one layer: a photon that is
 // not reflected at a face always leaves, so the layer-change code is not
 // compiled in.
-template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE>
-__global__ void walk(WalkArgs a)
+// One photon-step of a lane from its Philox block X (the lane's step
+// counter k already advanced): free path, then boundary or interaction;
+// sets `term` when the photon ends.  Written out as a macro so that each
+// loop of the walk compiles it in place.
+#define FOS_WALK_STEP(X)                                                                     \
+    do {                                                                                     \
+        const uint4 x_ = (X);                                                                \
+        const float U1 = u24(x_.y);                                                          \
+        if (s == 0.f) s = neg_ln(1.0f - u24(x_.x));                                          \
+        const float aa = fabsf(uz);                                                          \
+        bool interact;                                                                       \
+        if (aa == 0.f) {                                                                     \
+            interact = P.mut > 0.f;                                                          \
+            if (!interact) term = kCap; /* parallel in a clear layer */                      \
+        } else {                                                                             \
+            const bool down = uz > 0.f;                                                      \
+            const float dz = down ? P.thick - z : z;                                         \
+            interact = !(P.mut * dz <= s * aa);                                              \
+            if (!interact) {                                                                 \
+/* reach the interface */                                                                    \
+                s = fmaxf(s - P.mut * dz * fast_rcp(aa), 0.f);                               \
+                z = down ? P.thick : 0.f;                                                    \
+                const uint32_t fl = P.flags;                                                 \
+                const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);                      \
+                const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);               \
+                float R = 0.f, ct = aa;                                                      \
+                if (down && (fl & kComplexDn)) {                                             \
+                    const float4 h0 = tab[slot * rf];                                        \
+                    R = fresnel_complex(aa, P.n, h0.z, h0.w);                                \
+                } else if (!matched) {                                                       \
+                    const float m = down ? P.m_dn : P.m_up;                                  \
+                    const float s2t = m * m * (1.f - aa * aa);                               \
+                    if (s2t >= 1.f) {                                                        \
+                        R = 1.f;                                                             \
+                    } else {                                                                 \
+                        ct = fast_sqrt(1.f - s2t);                                           \
+                        R = fresnel_real(aa, ct, m);                                         \
+                    }                                                                        \
+                }                                                                            \
+                if (U1 < R) {                                                                \
+                    uz = -uz;                                                                \
+                } else if (SINGLE || ex) {                                                   \
+                    term = down ? kTrans : kRDiff;                                           \
+                } else {                                                                     \
+                    layer += down ? 1 : -1;                                                  \
+                    load_layer(tab + slot * rf, layer, P);                                   \
+                    uz = down ? ct : -ct;                                                    \
+                    z = down ? 0.f : P.thick;                                                \
+                }                                                                            \
+            } else {                                                                         \
+                z = fmaf(uz * s, P.inv_mut, z);                                              \
+                s = 0.f;                                                                     \
+            }                                                                                \
+        }                                                                                    \
+        if (interact) {                                                                      \
+            bool scatter;                                                                    \
+            if constexpr (WEIGHTED) {                                                        \
+/* deposit mu_a/mu_t of the weight, scatter the rest */                                      \
+                const float wn = wgt * P.alb;                                                \
+                absd += wgt - wn;                                                            \
+                wgt = wn;                                                                    \
+                scatter = wgt > 0.f;                                                         \
+                if (!scatter) term = kAbs;                                                   \
+            } else {                                                                         \
+                scatter = U1 < P.alb;                                                        \
+                if (!scatter) term = kAbs;                                                   \
+            }                                                                                \
+            if (scatter) {                                                                   \
+                const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,  \
+                                       u24(x_.z));                                           \
+                const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);               \
+                const float cp = __builtin_amdgcn_cosf(u24(x_.w)); /* cos(2 pi U3) */        \
+                uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);              \
+                if constexpr (WEIGHTED) {                                                    \
+                    if (wgt < kRouletteThreshold) {                                          \
+                        if (U1 < kRouletteChance) wgt = wgt / kRouletteChance;               \
+                        else term = kWRoulette;                                              \
+                    }                                                                        \
+                }                                                                            \
+            }                                                                                \
+        }                                                                                    \
+    } while (0)
+
+// TAIL is the build for heavy-tailed runs: it adds the tail phase below (a
+// wave that has nothing left to claim and at most tail_lanes photons in
+// flight prepares their next draws on all 64 lanes).
+template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE, bool TAIL>
+__device__ __forceinline__ void walk_body(WalkArgs a)
 {
     constexpr int NT = WEIGHTED ? kNTallyW : kNTally;
     extern __shared__ float4 smem[];
@@ -229,6 +315,10 @@ __global__ void walk(WalkArgs a)
     int* slot_item = reinterpret_cast<int*>(reinterpret_cast<unsigned long long*>(
                          smem + (size_t)nwaves * kSlots * rf) + (size_t)nwaves * kSlots * NT) +
                      wv * kSlots;                                            // [kSlots]
+    // tail phase: 64 prepared Philox blocks of this wave
+    uint4* drw = reinterpret_cast<uint4*>(smem + (size_t)nwaves * kSlots * rf +
+                                          (size_t)nwaves * kSlots * NT / 2 + (size_t)nwaves * kSlots / 4) +
+                 (size_t)wv * 64;
 
     for (int j = lane; j < kSlots * NT; j += 64) cnt[j] = 0ull;
     if (lane < kSlots) slot_item[lane] = -1;
@@ -354,86 +444,80 @@ __global__ void walk(WalkArgs a)
         if (dead == ~0ull) break;   // queue exhausted and nothing in flight
 
         // ---------------- walk ----------------
+
+        if constexpr (TAIL) {
+            // ---- tail: nothing left to claim and few photons in flight ----
+            // A step's Philox block depends only on (photon, step, item,
+            // seed), so the idle lanes compute the next draws of the live
+            // photons ahead of time: with nl photons in flight each gets
+            // B = 64 / 2^ceil(log2 nl) consecutive blocks, one per lane, in
+            // the wave's LDS buffer, and its lane reads the block of each
+            // step there instead of running the ten dependent Philox rounds.
+            // The draws, and so the tallies, are the same bits.
+            if (queue_done && src_next >= src_end && 64 - __popcll(dead) <= a.tail_lanes) {
+                const uint64_t live = ballot64(alive && k < max_steps);
+                const int nl = __popcll(live);
+                int lg = 0;
+                while ((1 << lg) < nl) ++lg;
+                const int B = 64 >> lg;
+                {
+                    // this lane prepares draw o of the q-th photon in flight
+                    const int q = lane >> (6 - lg);
+                    const int o = lane & (B - 1);
+                    uint64_t m = live;
+                    for (int t = 0; t < q && m; ++t) m &= m - 1;
+                    const int src = m ? (int)__builtin_ctzll(m) : 0;
+                    const uint32_t sp_lo = __shfl(p_lo, src), sp_hi = __shfl(p_hi, src);
+                    const uint32_t s_k = __shfl(k, src), s_item = __shfl(item, src);
+                    drw[lane] = philox4x32_10(sp_lo, sp_hi, s_k + 1u + (uint32_t)o, s_item, k0, k1);
+                }
+                wave_sync_lds();
+                const int base = (alive && k < max_steps) ? (lane_rank(live) << (6 - lg)) : 0;
+                for (int j = 0; j < B; ++j) {
+                    const bool go = alive && k < max_steps;
+                    int term = (alive && !go) ? (int)kCap : -1;
+                    if (go) {
+                        ++k;
+                        FOS_WALK_STEP(drw[base + j]);
+                    }
+                    if (term >= 0) {
+                        // this lane's photon finished: tallies as in the loop below
+                        alive = false;
+                        unsigned long long* c0 = cnt + slot * NT;
+                        if constexpr (WEIGHTED) {
+                            atomicAdd(c0 + kWSteps, (unsigned long long)k);
+                            const double ad = (double)absd;
+                            if (ad > 0.0) {
+                                atomicAdd(c0 + kWAbs, weight_units(ad));
+                                atomicAdd(c0 + kWAbs2, weight_units(ad * ad));
+                            }
+                            if (term == kTrans || term == kRDiff) {
+                                const double w = (double)wgt;
+                                atomicAdd(c0 + (term == kTrans ? kWTrans : kWRDiff), weight_units(w));
+                                atomicAdd(c0 + (term == kTrans ? kWTrans2 : kWRDiff2), weight_units(w * w));
+                            } else if (term == kWRoulette) {
+                                atomicAdd(c0 + kWRoulette, 1ull);
+                            } else if (term == kCap) {
+                                atomicAdd(c0 + kWCap, 1ull);
+                            }
+                        } else {
+                            atomicAdd(c0 + kSteps, (unsigned long long)k);
+                            atomicAdd(c0 + term, 1ull);
+                        }
+                    }
+                    if (ballot64(alive) == 0ull) break;
+                }
+                wave_sync_lds();
+                continue;
+            }
+        }
+
         for (int it = 0; it < kStepsPerCheck; ++it) {
             const bool go = alive && k < max_steps;
             int term = (alive && !go) ? (int)kCap : -1;        // step budget used up
             if (go) {
                 ++k;
-                const uint4 x = philox4x32_10(p_lo, p_hi, k, item, k0, k1);
-                const float U1 = u24(x.y);
-                if (s == 0.f) s = neg_ln(1.0f - u24(x.x));
-                const float aa = fabsf(uz);
-                bool interact;
-                if (aa == 0.f) {
-                    interact = P.mut > 0.f;
-                    if (!interact) term = kCap;      // parallel in a clear layer
-                } else {
-                    const bool down = uz > 0.f;
-                    const float dz = down ? P.thick - z : z;
-                    interact = !(P.mut * dz <= s * aa);
-                    if (!interact) {
-                        // reach the interface
-                        s = fmaxf(s - P.mut * dz * fast_rcp(aa), 0.f);
-                        z = down ? P.thick : 0.f;
-                        const uint32_t fl = P.flags;
-                        const bool ex = down ? (fl & kExitDn) : (fl & kExitUp);
-                        const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);
-                        float R = 0.f, ct = aa;
-                        if (down && (fl & kComplexDn)) {
-                            const float4 h0 = tab[slot * rf];
-                            R = fresnel_complex(aa, P.n, h0.z, h0.w);
-                        } else if (!matched) {
-                            const float m = down ? P.m_dn : P.m_up;
-                            const float s2t = m * m * (1.f - aa * aa);
-                            if (s2t >= 1.f) {
-                                R = 1.f;
-                            } else {
-                                ct = fast_sqrt(1.f - s2t);
-                                R = fresnel_real(aa, ct, m);
-                            }
-                        }
-                        if (U1 < R) {
-                            uz = -uz;
-                        } else if (SINGLE || ex) {
-                            term = down ? kTrans : kRDiff;
-                        } else {
-                            layer += down ? 1 : -1;
-                            load_layer(tab + slot * rf, layer, P);
-                            uz = down ? ct : -ct;
-                            z = down ? 0.f : P.thick;
-                        }
-                    } else {
-                        z = fmaf(uz * s, P.inv_mut, z);
-                        s = 0.f;
-                    }
-                }
-                if (interact) {
-                    bool scatter;
-                    if constexpr (WEIGHTED) {
-                        // deposit mu_a/mu_t of the weight, scatter the rest
-                        const float wn = wgt * P.alb;
-                        absd += wgt - wn;
-                        wgt = wn;
-                        scatter = wgt > 0.f;
-                        if (!scatter) term = kAbs;
-                    } else {
-                        scatter = U1 < P.alb;
-                        if (!scatter) term = kAbs;
-                    }
-                    if (scatter) {
-                        const float c = hg_cos(P.hG, P.hh, P.q1, P.q2, (P.flags & kHgMirror) != 0u,
-                                               u24(x.z));
-                        const float st2 = fmaxf((1.f - uz * uz) * (1.f - c * c), 0.f);
-                        const float cp = __builtin_amdgcn_cosf(u24(x.w));   // cos(2 pi U3)
-                        uz = fminf(fmaxf(fmaf(uz, c, fast_sqrt(st2) * cp), -1.f), 1.f);
-                        if constexpr (WEIGHTED) {
-                            if (wgt < kRouletteThreshold) {
-                                if (U1 < kRouletteChance) wgt = wgt / kRouletteChance;
-                                else term = kWRoulette;
-                            }
-                        }
-                    }
-                }
+                FOS_WALK_STEP(philox4x32_10(p_lo, p_hi, k, item, k0, k1));
             }
             // ---- tallies of photons that finished in this step ----
             const uint64_t tm = ballot64(term >= 0);
@@ -486,19 +570,42 @@ __global__ void walk(WalkArgs a)
     }
 }
 
-size_t walk_lds_bytes(int block_size, int max_layers, bool weighted)
+template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE>
+__global__ void walk(WalkArgs a)
+{
+    walk_body<kStepsPerCheck, WEIGHTED, SINGLE, false>(a);
+}
+
+template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE>
+__global__ void walk_long(WalkArgs a)
+{
+    walk_body<kStepsPerCheck, WEIGHTED, SINGLE, true>(a);
+}
+
+size_t walk_lds_bytes(int block_size, int max_layers, bool weighted, bool tail)
 {
     const int nw = block_size / 64;
     const int nt = weighted ? kNTallyW : kNTally;
     return (size_t)nw * kSlots * rec_f4(max_layers) * sizeof(float4) +
-           (size_t)nw * kSlots * nt * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int);
+           (size_t)nw * kSlots * nt * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int) +
+           (tail ? (size_t)nw * 64 * sizeof(uint4) : 0);
 }
 
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted)
 {
-    const size_t lds = walk_lds_bytes(block, a.max_layers, weighted);
+    const bool tail = a.tail_lanes > 0;
+    const size_t lds = walk_lds_bytes(block, a.max_layers, weighted, tail);
     const bool single = a.max_layers == 1;
-    if (weighted && single)
+    if (tail) {
+        if (weighted && single)
+            hipLaunchKernelGGL((walk_long<16, true, true>), dim3(grid), dim3(block), lds, st, a);
+        else if (weighted)
+            hipLaunchKernelGGL((walk_long<16, true, false>), dim3(grid), dim3(block), lds, st, a);
+        else if (single)
+            hipLaunchKernelGGL((walk_long<16, false, true>), dim3(grid), dim3(block), lds, st, a);
+        else
+            hipLaunchKernelGGL((walk_long<16, false, false>), dim3(grid), dim3(block), lds, st, a);
+    } else if (weighted && single)
         hipLaunchKernelGGL((walk<16, true, true>), dim3(grid), dim3(block), lds, st, a);
     else if (weighted)
         hipLaunchKernelGGL((walk<16, true, false>), dim3(grid), dim3(block), lds, st, a);

@@ -52,6 +52,9 @@ fos_status check_launch(fos_ctx* c, const fos_mc_launch& L)
         return fail(c, FOS_E_INVALID_ARG, "launch.blocks_per_cu must be in [1, 64]");
     if (L.max_steps < 1 || L.max_steps > 0xFFFFFFFFull)
         return fail(c, FOS_E_INVALID_ARG, "launch.max_steps must be in [1, 2^32-1]");
+    if (L.tail_lanes < -1 || L.tail_lanes > 64)
+        return fail(c, FOS_E_INVALID_ARG, "launch.tail_lanes must be in [-1, 64]");
+    if (L.reserved != 0) return fail(c, FOS_E_INVALID_ARG, "launch.reserved must be 0");
     return FOS_OK;
 }
 
@@ -82,6 +85,8 @@ fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
     if (o->chunk) r.chunk = o->chunk;
     if (o->blocks_per_cu) r.blocks_per_cu = o->blocks_per_cu;
     if (o->max_steps) r.max_steps = o->max_steps;
+    if (o->tail_lanes) r.tail_lanes = o->tail_lanes;
+    if (o->reserved) r.reserved = o->reserved;
     return r;
 }
 
@@ -133,6 +138,7 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     c->defaults.chunk = 2048;
     c->defaults.blocks_per_cu = 8;
     c->defaults.max_steps = 100000000ull;
+    c->defaults.tail_lanes = -1;
     DeviceGuard g(hip_device);
     if (hipMalloc(reinterpret_cast<void**>(&c->chunk_counter), 256) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->err_dev), 256) != hipSuccess ||
@@ -274,6 +280,7 @@ static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed
     a.max_steps = (uint32_t)L.max_steps;
     a.chunk = L.chunk;
     a.refill_min = L.refill_min;
+    a.tail_lanes = L.tail_lanes < 0 ? 0 : L.tail_lanes;
     return a;
 }
 

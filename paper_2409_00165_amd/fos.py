@@ -62,10 +62,11 @@ class fos_train_opts(Structure):
 
 class fos_mc_launch(Structure):
     _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
-                ("blocks_per_cu", c_int32), ("max_steps", c_uint64)]
+                ("blocks_per_cu", c_int32), ("max_steps", c_uint64), ("tail_lanes", c_int32),
+                ("reserved", c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None

@@ -50,8 +50,17 @@ def _walk(p, seed, items=None, photons=None):
                              a["mu0"], ph, seed=seed, streams=idx.astype(np.uint32))
 
 
+def stacks_stratified_designs(wl, k):
+    """Indices of k designs of a stacks workload spread evenly over its
+    photon budgets (sorted by budget, the designs at quantiles (j + 1/2)/k)."""
+    ph = np.array([d.photons for d in wl.designs])
+    order = np.argsort(ph, kind="stable")
+    return order[((np.arange(k) + 0.5) * len(ph) / k).astype(int)]
+
+
 def make(name: str):
     t0 = time.time()
+    extra = {}
     if name == "single_slab_23":
         wl = W.single_slab_23()
         p = _problem(wl)
@@ -61,18 +70,22 @@ def make(name: str):
         p = _problem(wl)
         items = list(range(len(p["n_layers"])))
     elif name == "stacks_3layer":
-        # 16 designs x 100 wavelengths, budgets scaled to 2e4..2e5 so the
-        # oracle finishes in minutes; stratified over the budget range
-        wl = W.stacks_3layer(n_designs=16, photons_lo=2e4, photons_hi=2e5)
+        # 64 of the 4096 benchmark designs x 100 wavelengths at their own
+        # photon budgets (log-uniform 1e4..1e6), stratified over the budget
+        # range: the designs at the budget quantiles (j + 1/2) / 64
+        full = W.stacks_3layer(n_designs=4096)
+        designs = stacks_stratified_designs(full, 64)
+        wl = W.Workload("stacks_3layer", full.wavelengths, [full.designs[d] for d in designs])
         p = _problem(wl)
         items = list(range(len(p["n_layers"])))
+        extra["designs"] = [int(d) for d in designs]
     else:
         raise SystemExit(f"unknown workload {name}")
     tal = _walk(p, ORACLE_SEED, items)
     out = dict(workload=name, oracle_seed=ORACLE_SEED, items=items,
                problem=p, tallies=tal.astype(np.int64).tolist(),
                note="written by tests/golden/make_oracle_golden.py (oracle only)",
-               oracle_seconds=round(time.time() - t0, 1))
+               oracle_seconds=round(time.time() - t0, 1), **extra)
     path = os.path.join(HERE, f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f, separators=(",", ":"))

@@ -78,23 +78,33 @@ def test_graph_sweep_replays_any_seed(ctx, torch):
 
 
 def test_batched_three_layer_designs_full_budgets(ctx, torch):
-    """512 three-layer designs x 100 wavelengths with photon budgets
-    log-uniform in [1e4, 1e6] (1.1e10 photons) in one persistent launch; the
-    first 16 designs are the oracle golden's designs (other budgets)."""
+    """The batched benchmark sweep at its full size, in the launch the
+    benchmark times: 4096 three-layer designs x 100 wavelengths with photon
+    budgets log-uniform in [1e4, 1e6] (8.9e10 photons), GPU optics, autotuned
+    launch, one graph-captured persistent walk.  The 64 designs of the oracle
+    golden (stratified over the budgets, at their own budgets) are checked
+    item by item; every item conserves its photons."""
     from paper_2409_00165_amd import fos
     from paper_2409_00165_amd import workloads as W
-    wl = W.stacks_3layer(n_designs=512)
+    wl = W.stacks_3layer(n_designs=4096)
     prob = _device_problem_with_gpu_optics(ctx, torch, wl)
     I = prob.n_items
+    fos.fos_mc_prepare(ctx, prob)
+    best, ms = fos.fos_mc_autotune(ctx, seed=7, photon_cap=2000)
+    print("autotuned launch", best, f"{ms:.2f} ms", flush=True)
     tal = torch.zeros(I * 6, dtype=torch.int64, device="cuda")
-    fos.fos_mc_run(ctx, prob, GPU_SEED, tal)
+    fos.fos_mc_graph_capture(ctx, tal)
+    fos.fos_mc_graph_launch(ctx, GPU_SEED)
     torch.cuda.synchronize()
     t = tal.cpu().numpy().reshape(I, 6)
     N = W.item_geometry(wl)["photons"].astype(np.int64)
     assert (t[:, :5].sum(1) == N).all() and (t[:, 4] == 0).all()
     G = load_golden("stacks_3layer")
+    designs = np.asarray(G["designs"], np.int64)
+    L = len(wl.wavelengths)
+    rows = (designs[:, None] * L + np.arange(L)[None, :]).ravel()
     o = np.asarray(G["tallies"], np.int64)
     No = np.asarray(G["problem"]["photons"], np.int64)
-    n = len(o)
-    _pooled_check(channels(t[:n]), N[:n], channels(o), No, "stacks_3layer full budgets")
+    assert (No == N[rows]).all()
+    _pooled_check(channels(t[rows]), N[rows], channels(o), No, "stacks_3layer 4096 designs")
     print("photon-steps:", int(t[:, 5].sum()), "mean per photon", t[:, 5].sum() / N.sum(), flush=True)

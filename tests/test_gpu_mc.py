@@ -37,22 +37,35 @@ def ctx(torch):
     c.close()
 
 
-def _pooled_check(g_counts, n_g, o_counts, n_o, label, k=4.0):
+def _pooled_check(g_counts, n_g, o_counts, n_o, label, k=4.0, alpha=1e-3):
+    """Two independent samples of every (item, channel) proportion agree
+    within k pooled binomial standard errors.  Under exact agreement each
+    channel exceeds k with probability P(|z| > k) (6.3e-5 at k = 4), so a
+    comparison of m channels sees about m * 6.3e-5 such channels by chance:
+    0.1 on a 500-wavelength spectrum, about 1 on 6400 items.  The test
+    therefore allows as many channels beyond k as a Poisson count of that
+    mean reaches with probability 1 - alpha, and none beyond the
+    family-wise bound k_fw (every channel inside it with probability 1 -
+    alpha); the aggregate chi^2 over all channels bounds the rest."""
+    from scipy.stats import norm, poisson
     g_counts = np.asarray(g_counts, np.float64); o_counts = np.asarray(o_counts, np.float64)
     n_g = np.asarray(n_g, np.float64)[:, None]; n_o = np.asarray(n_o, np.float64)[:, None]
     d = np.abs(g_counts / n_g - o_counts / n_o)
-    b = pooled_bound(g_counts, n_g, o_counts, n_o, k=k)
-    worst = np.unravel_index(np.argmax(d / np.maximum(b, 1e-300)), d.shape)
-    print(f"{label}: max |dp| = {d.max():.3e}, worst z/4 = {(d / np.maximum(b, 1e-300)).max():.3f} at {worst}",
-          flush=True)
+    se = pooled_bound(g_counts, n_g, o_counts, n_o, k=1.0)
     both_zero = (g_counts == 0) & (o_counts == 0)
-    assert ((d <= b) | both_zero).all(), f"{label}: channel outside 4 pooled SE at {worst}"
-    # aggregate chi^2 over (item, channel) of the two-sample z scores
-    se = b / k
-    z = np.where(se > 0, (g_counts / n_g - o_counts / n_o) / np.where(se > 0, se, 1), 0.0)
-    m = se > 0
-    chi2, dof = float((z[m] ** 2).sum()), int(m.sum())
-    print(f"{label}: aggregate chi2 = {chi2:.1f} over {dof} channels", flush=True)
+    live = (se > 0) & ~both_zero
+    z = np.where(live, d / np.where(live, se, 1.0), 0.0)
+    m = int(live.sum())
+    k_fw = max(k, float(norm.isf(alpha / (2 * max(m, 1)))))
+    beyond = int((z > k).sum())
+    allowed = int(poisson.ppf(1.0 - alpha, m * 2 * norm.sf(k)))
+    worst = np.unravel_index(np.argmax(z), z.shape)
+    chi2, dof = float((z[live] ** 2).sum()), m
+    print(f"{label}: max |dp| = {d.max():.3e}, max z = {z.max():.2f} at {worst}; {beyond} of {m} channels "
+          f"beyond {k:g} SE (allowed {allowed}), family-wise bound {k_fw:.2f}; chi2 = {chi2:.1f} over {dof}",
+          flush=True)
+    assert ((z <= k_fw) | ~live).all(), f"{label}: channel beyond {k_fw:.2f} pooled SE at {worst}"
+    assert beyond <= allowed, f"{label}: {beyond} channels beyond {k:g} pooled SE (allowed {allowed})"
     assert chi2 < dof + 6 * math.sqrt(2 * dof) + 10
 
 
@@ -100,8 +113,18 @@ def test_fresnel_device_matches_oracle(ctx, torch, orc):
     err = np.abs(got - ref)
     print("fresnel max abs err", err.max(), flush=True)
     assert err.max() < 3e-6
-    tir = ref == 1.0     # total internal reflection (float ratio may sit a hair below it)
-    assert (got[tir] >= 1.0 - 3e-6).all()
+    # total internal reflection clear of the critical angle: exactly 1 on the
+    # device too (its TIR branch); within a few FP32 ulp of the critical
+    # cosine the float ratio m = ni/nt may put the device on the other side,
+    # where R is continuous and tends to 1, and at grazing incidence (c = 0)
+    # R = 1 comes out of the approximate reciprocal and square root (~1 ulp)
+    c, ni, nt, kt = (a[:, i].astype(np.float64) for i in range(4))
+    s2t = (ni / nt) ** 2 * (1.0 - c * c)
+    tir = (kt == 0) & (c > 0) & (s2t >= 1.0 + 1e-5)
+    assert tir.sum() > 50 and (ref[tir] == 1.0).all()
+    assert (got[tir] == 1.0).all()
+    graze = (c == 0) | (np.abs(s2t - 1.0) < 1e-5)
+    assert (got[ref == 1.0] >= 1.0 - 3e-6).all() and (np.abs(got[graze] - ref[graze]) < 3e-6).all()
 
 
 def test_hg_device_matches_oracle(ctx, torch, orc):
@@ -316,11 +339,56 @@ def test_bit_identical_across_launch_configs(ctx, torch):
     for launch in ({"block_size": 64, "refill_min": 1, "chunk": 1, "blocks_per_cu": 1},
                    {"block_size": 1024, "refill_min": 64, "chunk": 37, "blocks_per_cu": 2},
                    {"block_size": 256, "refill_min": 8, "chunk": 1 << 20, "blocks_per_cu": 8},
-                   {"block_size": 512, "refill_min": 32, "chunk": 4096, "blocks_per_cu": 4}):
+                   {"block_size": 512, "refill_min": 32, "chunk": 4096, "blocks_per_cu": 4},
+                   {"tail_lanes": -1}, {"tail_lanes": 1}, {"tail_lanes": 64},
+                   {"block_size": 64, "refill_min": 3, "chunk": 5, "blocks_per_cu": 1, "tail_lanes": 40}):
         t = run_gpu(ctx, a, 1234, launch=launch)
         assert (t == ref).all(), launch
     assert (run_gpu(ctx, a, 1234) == ref).all()
     assert not (run_gpu(ctx, a, 1235) == ref).all()
+
+
+def _heavy_tail_problem(layers):
+    """Thick, weakly absorbing slabs (walks of 1e4..1e6 steps, many beyond a
+    cap of 5e4) mixed with thin ones, so that the end of a launch is a few
+    long walks in otherwise idle waves."""
+    rng = np.random.default_rng(41)
+    I = 48
+    tau = np.where(np.arange(I) % 3 == 0, rng.uniform(300, 1500, I), rng.uniform(0.1, 20, I))
+    t = np.full((I, layers), 100.0 / layers)
+    return make_arrays(np.repeat(tau[:, None] / 100.0, layers, 1), np.full((I, layers), 1e-7),
+                       rng.uniform(-0.2, 0.9, (I, layers)), rng.uniform(1.0, 1.6, (I, layers)), t,
+                       n_lower=rng.uniform(1, 2, I), k_lower=np.where(np.arange(I) % 4 == 0, 0.01, 0.0),
+                       mu0=rng.uniform(0.5, 1.0, I), photons=rng.integers(200, 3000, I))
+
+
+@pytest.mark.parametrize("layers", [1, 2])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_tail_draws_prepared_across_lanes_are_bit_identical(ctx, torch, layers, weighted):
+    """At the end of a launch, a wave with no photons left to claim and few in
+    flight computes their next draws on all its lanes ahead of time (any
+    tail_lanes threshold, or never): the tallies are the same bits, including
+    the photons stopped by the step cap."""
+    from paper_2409_00165_amd import fos
+    from gpu_helpers import device_problem
+    a = _heavy_tail_problem(layers)
+    prob = device_problem(a)
+    nt = fos.N_TALLY_W if weighted else fos.N_TALLY
+    run = fos.fos_mc_run_weighted if weighted else fos.fos_mc_run
+    outs = []
+    for tail in (-1, 1, 4, 8, 16, 33, 64):
+        tal = torch.full((prob.n_items * nt,), -1, dtype=torch.int64, device="cuda")
+        run(ctx, prob, 777, tal, launch={"tail_lanes": tail, "max_steps": 50_000, "chunk": 64})
+        torch.cuda.synchronize()
+        outs.append(tal.cpu().numpy().reshape(prob.n_items, nt))
+    for o in outs[1:]:
+        assert (o == outs[0]).all()
+    t = outs[0]
+    capped = t[:, 8] if weighted else t[:, 4]
+    steps = t[:, 9] if weighted else t[:, 5]
+    print("capped photons", int(capped.sum()), "max mean steps per photon", float((steps / a["photons"]).max()),
+          flush=True)
+    assert capped.sum() > 0 and (steps / a["photons"]).max() > 1e3
 
 
 def test_per_problem_chunk_keeps_results(torch):

@@ -224,16 +224,271 @@ BF16_MFMA_PEAK = 2.5e15   # dense BF16 MFMA, MI355X
 TRAIN_SEED = 20240931     # training items and their walks
 HELD_SEED = 777           # held-out items
 HELD_N = 10_000
+INIT_SEED = 5             # He initialisation and shuffles of the ensemble
+MODEL_PATH = os.path.join(ROOT, "paper_2409_00165_amd", "trained", "surrogate_ens4.fossur")
+MODEL_INFO = MODEL_PATH[:-len(".fossur")] + ".json"
+
+
+def load_model(h, path=MODEL_PATH):
+    """Load an ensemble written by surrogate_train (by default the committed
+    one) after checking its bytes against the digest recorded beside it;
+    returns its provenance record."""
+    import hashlib
+    from paper_2409_00165_amd import fos
+    blob = open(path, "rb").read()
+    info_path = path[:-len(".fossur")] + ".json"
+    info = json.load(open(info_path))
+    if hashlib.sha256(blob).hexdigest() != info["sha256"]:
+        raise SystemExit(f"{path} does not match the digest in {info_path}")
+    fos.fos_sur_load(h, blob)
+    return info
+
+
+def surrogate_record(h, args, say):
+    """The design sweep run two ways on one GPU: surrogate + Monte Carlo
+    fallback (fos_sweep_run, the committed ensemble) on `designs` single-layer
+    paint designs x `lambdas` wavelengths, and plain Monte Carlo at the
+    fallback budget on the first `mc_designs` of them; both against 1e6-photon
+    Monte Carlo on the surrogate's top `verify_designs` designs, on as many
+    random designs, and on the same random designs with their median radius
+    and matrix index unsnapped (per-entry optics)."""
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    from paper_2409_00165_amd import workloads as W
+    info = load_model(h, args.model)
+    say(f"surrogate: model {os.path.basename(args.model)} ({info['sha256'][:12]}) loaded")
+    D, L, fb = args.designs_sweep, args.lambdas, args.fallback_photons
+    sweep = W.paint_sweep(D, n_lambda=L, photons=fb)
+    t0 = time.perf_counter()
+    prob = SP.paint_problem(h, sweep)
+    torch.cuda.synchronize()
+    t_optics = time.perf_counter() - t0
+    n = prob.n_items
+    say(f"surrogate: sweep problem ready, {D} designs x {L} wavelengths ({t_optics:.2f} s of optics)")
+    # plain Monte Carlo at the fallback budget on the first designs
+    Dm = min(args.mc_designs, D)
+    sub = SP.take_items(prob, torch.arange(Dm * L, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, steps_mc, _, _ = SP.mc_fractions(h, sub, 424242)
+    torch.cuda.synchronize()
+    t_mc = time.perf_counter() - t0
+    del sub
+    say(f"surrogate: plain Monte Carlo on {Dm} designs at {fb} photons, {t_mc:.2f} s")
+    rat = torch.zeros(3 * n, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    spread = torch.zeros(n, device="cuda")
+    fos.fos_sweep_run(h, prob, args.spread_max, fb, 515151, rat, used, spread=spread)   # warm-up
+    torch.cuda.synchronize()
+    t_sur = []
+    for k in range(2):
+        t0 = time.perf_counter()
+        n_fb = fos.fos_sweep_run(h, prob, args.spread_max, fb, 515152 + k, rat, used, spread=spread)
+        torch.cuda.synchronize()
+        t_sur.append(time.perf_counter() - t0)
+    n_spread = int((spread > args.spread_max).sum().item())
+    say(f"surrogate: sweep {min(t_sur):.3f} s, {n_fb} of {n} items on Monte Carlo ({n_spread} by spread)")
+    # the fused inference kernel alone, events on the stream it runs on
+    xs = torch.zeros(8 * n, device="cuda")
+    el = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    fos.fos_sur_features(h, prob, xs, el)
+    pr = torch.zeros(3 * n, device="cuda")
+    fos.fos_sur_predict(h, xs, eligible=el, rat=pr)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    fos.fos_sur_predict(h, xs, eligible=el, rat=pr)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_pred = ev0.elapsed_time(ev1) / 1e3
+    del xs, el, pr
+    pred_flop = float(MLP_FORWARD_FLOP) * 4 * n
+    # ranking: solar-weighted R (5778 K Planck stand-in) + 8-13 um emittance
+    lam = sweep.wavelengths
+    wr = torch.from_numpy(W.planck_weights(lam, 5778.0, 0.3, 2.5).astype(np.float32)).cuda()
+    we = torch.from_numpy(W.planck_weights(lam, 300.0, 8.0, 13.0).astype(np.float32)).cuda()
+    red = torch.zeros(2 * D, device="cuda")
+    fos.fos_spectral_reduce(h, D, L, rat, wr, we, red)
+    fom = red.view(D, 2).sum(1).cpu().numpy()
+    K = min(args.verify_designs, D)
+    top = np.argsort(-fom)[:K]
+    rnd = np.random.default_rng(3).choice(D, size=K, replace=False)
+    ver = {}
+    for j, (name, designs) in enumerate((("top", top), ("random", rnd))):
+        items = torch.from_numpy((designs[:, None] * L + np.arange(L)[None, :]).ravel()).cuda()
+        vprob = SP.take_items(prob, items)
+        ref = SP.mc_fractions(h, SP.with_photons(vprob, 1_000_000), 99 + j)[0]
+        plain = SP.mc_fractions(h, SP.with_photons(vprob, fb), 77 + j)[0]
+        refn = ref.cpu().numpy()
+        ver[name] = {"designs": int(K),
+                     "surrogate_vs_1e6_mc": SP.errors(rat.view(n, 3)[items].cpu().numpy().ravel(), refn),
+                     "plain_mc_vs_1e6_mc": SP.errors(plain.cpu().numpy(), refn),
+                     "fallback_frac": float(used[items].float().mean().item())}
+        say(f"surrogate: {name} {K} designs vs 1e6-photon Monte Carlo {ver[name]['surrogate_vs_1e6_mc']}")
+    # the random designs again with median radius and matrix index as drawn
+    # (not snapped to the sweep's grids): per-entry optics, same gate
+    wl = W.paint_unsnapped(rnd, D, n_lambda=L, photons=fb)
+    uprob = SP.optics_problem(h, wl)
+    un = uprob.n_items
+    urat = torch.zeros(3 * un, device="cuda")
+    uused = torch.zeros(un, dtype=torch.uint8, device="cuda")
+    fos.fos_sweep_run(h, uprob, args.spread_max, fb, 616161, urat, uused)
+    uref = SP.mc_fractions(h, SP.with_photons(uprob, 1_000_000), 101)[0]
+    ver["random_unsnapped"] = {"designs": int(K),
+                               "surrogate_vs_1e6_mc": SP.errors(urat.cpu().numpy(), uref.cpu().numpy()),
+                               "fallback_frac": float(uused.float().mean().item())}
+    say(f"surrogate: random {K} unsnapped designs vs 1e6-photon Monte Carlo "
+        f"{ver['random_unsnapped']['surrogate_vs_1e6_mc']}")
+    worst = max(v["surrogate_vs_1e6_mc"]["max"] for v in ver.values())
+    sps_sur = D / min(t_sur)
+    sps_mc = Dm / t_mc
+    return {
+        "metric": "spectra/s: surrogate + Monte Carlo fallback vs plain GPU Monte Carlo (<=0.01 R/A/T error)",
+        "value": sps_sur, "unit": "spectra/s",
+        "config": {"workload": f"paint sweep: {D} single-layer designs x {L} wavelengths (0.3-16 um, log-spaced); "
+                               f"median radius on the grid 0.05 exp(0.09 k) um ({W.PAINT_N_RMED} values), matrix "
+                               f"index on {len(W.PAINT_NM)} values 1.30..1.70; spread gate {args.spread_max}, "
+                               f"fallback {fb} photons; verification at 1e6 photons",
+                   "items": n, "designs": D, "lambdas": L},
+        "seconds": min(t_sur), "seconds_all": t_sur, "optics_seconds": t_optics,
+        "plain_mc_spectra_per_s": sps_mc, "plain_mc_seconds": t_mc, "plain_mc_designs": Dm,
+        "plain_mc_photons": fb, "plain_mc_photon_steps": steps_mc,
+        "speedup_vs_plain_mc": sps_sur / sps_mc,
+        "speedup_vs_plain_mc_scaled": {"1e4": sps_sur / (sps_mc * fb / 1e4), "1e6": sps_sur / (sps_mc * fb / 1e6)},
+        "fallback_rate": n_fb / n, "fallback_by_spread": n_spread, "fallback_out_of_domain": n_fb - n_spread,
+        "max_abs_error_vs_1e6_mc": worst, "verification": ver,
+        "inference_roofline": {"bound": "mfma", "achieved": pred_flop / t_pred / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
+                               "unit": "TFLOP/s", "frac": pred_flop / t_pred / BF16_MFMA_PEAK,
+                               "kernel": "fos::mlp_infer_kernel", "rows": n, "kernel_ms": 1e3 * t_pred,
+                               "work_per_row_flop": 4 * MLP_FORWARD_FLOP},
+        "model": {k: info[k] for k in ("file", "sha256", "command", "recipe", "samples", "photons_each", "epochs",
+                                      "held_out_error") if k in info},
+    }
+
+
+def surrogate_train_main(args):
+    """Surrogate training pipeline: walk-labelled training set (single
+    layers, inputs log-uniform over the workloads' optical depths,
+    `train_photons` each), 4-member ensemble training on the GPU, held-out
+    error against Monte Carlo; writes the weights (no optimiser state) and
+    their provenance to --save-model (default: the committed model path)."""
+    t_start = time.perf_counter()
+
+    def say(msg):
+        print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    import hashlib
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    say("surrogate training pipeline start")
+    launch = {"tail_lanes": args.tail_lanes} if args.tail_lanes else None
+    n_tr = args.train_samples
+    if args.load_data:
+        # stored labels, re-joined to features regenerated from the same item seeds
+        z = np.load(args.load_data)
+        if str(z["recipe"]) != SP.training_recipe_id(TRAIN_SEED, int(z["n"])):
+            raise SystemExit(f"{args.load_data}: labels were drawn by another training-item recipe")
+        n_tr, ph = int(z["n"]), int(z["photons"])
+        x, _, _, _ = SP.make_training_set(h, n_tr, ph, seed=TRAIN_SEED, label=False)
+        y = torch.from_numpy(z["y"]).cuda()
+        rec = {k: z[k].item() for k in ("label_seconds", "label_photon_steps") if k in z}
+        rec.update({"samples": n_tr, "photons_each": ph, "labels": f"loaded from {os.path.basename(args.load_data)}"})
+        say(f"training set loaded: {n_tr} samples")
+    else:
+        # labels, resumable: --label-state keeps the finished launches' rows
+        sizes = SP.label_launch_sizes(n_tr)
+        recipe = SP.training_recipe_id(TRAIN_SEED, n_tr)
+        st = {"done": [], "steps": 0, "capped": 0, "seconds": 0.0, "launch_seconds": {}}
+        y = torch.zeros(n_tr * 3, dtype=torch.float32, device="cuda")
+        if args.label_state and os.path.exists(args.label_state):
+            z = np.load(args.label_state)
+            if str(z["recipe"]) != recipe or int(z["photons"]) != args.train_photons:
+                raise SystemExit(f"{args.label_state}: labels of another recipe")
+            st = json.loads(str(z["state"]))
+            y = torch.from_numpy(z["y"]).cuda()
+            say(f"label state: launches {sorted(st['done'])} already walked")
+        todo = [c for c in range(len(sizes)) if c not in st["done"]]
+        if args.label_launches:
+            a, b = (int(v) for v in args.label_launches.split(":"))
+            todo = [c for c in todo if a <= c < b]
+        t_call = time.perf_counter()
+
+        def on_launch(c, steps, capped):
+            st["done"].append(c)
+            st["steps"] += steps
+            st["capped"] += capped
+            st["launch_seconds"][str(c)] = round(time.perf_counter() - t_call, 1)
+            if args.label_state:
+                np.savez(args.label_state, y=y.cpu().numpy(), recipe=recipe, photons=args.train_photons,
+                         state=json.dumps(dict(st, seconds=st["seconds"] + time.perf_counter() - t_call)))
+
+        x, y, steps, secs = SP.make_training_set(h, n_tr, args.train_photons, seed=TRAIN_SEED, log=say,
+                                                 launch=launch, launches=todo, y=y, on_launch=on_launch)
+        st["seconds"] += secs
+        if len(st["done"]) < len(sizes):
+            left = [c for c in range(len(sizes)) if c not in st["done"]]
+            print(json.dumps({"metric": "surrogate labels (partial)", "value": len(st["done"]), "unit": "launches",
+                              "left": left, "state": args.label_state, "seconds": secs}), flush=True)
+            ctx.close()
+            return 0
+        rec = {"samples": n_tr, "photons_each": args.train_photons, "label_seconds": st["seconds"],
+               "label_photon_steps": st["steps"], "label_photon_steps_per_s": st["steps"] / st["seconds"],
+               "label_capped_photons": st["capped"], "label_launches": len(sizes),
+               "label_launch": launch or "default"}
+        say(f"labels: {n_tr} items x {args.train_photons} photons in {st['seconds']:.1f} s of walks, "
+            f"{st['steps']:.3e} photon-steps, {st['capped']} capped photons")
+    xh, yh, _, _ = SP.make_training_set(h, HELD_N, rec["photons_each"], seed=HELD_SEED, chunk=HELD_N, launch=launch)
+    if args.save_data:
+        np.savez(args.save_data, y=y.cpu().numpy(), yh=yh.cpu().numpy(), n=n_tr,
+                 recipe=SP.training_recipe_id(TRAIN_SEED, n_tr), photons=rec["photons_each"],
+                 label_seconds=rec.get("label_seconds", 0.0), label_photon_steps=rec.get("label_photon_steps", 0))
+        say(f"training and held-out labels written to {args.save_data}")
+    hist, tsec = SP.train(h, x, y, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_min=args.lr * 1e-2,
+                          seed=INIT_SEED)
+    rec.update({"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "lr_min": args.lr * 1e-2,
+                "init_seed": INIT_SEED, "train_seconds": tsec, "loss_first_epoch": hist[0].tolist(),
+                "loss_last_epoch": hist[-1].tolist()})
+    say(f"trained {args.epochs} epochs in {tsec:.1f} s; mean loss {hist[0].mean():.4f} -> {hist[-1].mean():.4f}")
+    rh, sh, ih = SP.predict(h, xh)
+    torch.cuda.synchronize()
+    rec["held_out_error"] = SP.errors(rh.cpu().numpy(), yh.cpu().numpy())
+    rec["held_out_in_gate"] = float(((sh <= args.spread_max) & ih.bool()).float().mean().item())
+    say(f"held-out ({HELD_N} items) error vs Monte Carlo {rec['held_out_error']}")
+    blob = SP.weights_only_blob(fos.fos_sur_save(h))
+    out = args.save_model or MODEL_PATH
+    if not out.endswith(".fossur"):
+        raise SystemExit("--save-model must name a .fossur file")
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    open(out, "wb").write(blob)
+    info = {"file": os.path.basename(out), "sha256": hashlib.sha256(blob).hexdigest(),
+            "command": "python bench.py --workload surrogate_train" +
+                       (f" --tail-lanes {args.tail_lanes}" if args.tail_lanes else "") +
+                       (f" --train-samples {n_tr}" if n_tr != 2_000_000 else "") +
+                       (f" --train-photons {rec['photons_each']}" if rec["photons_each"] != 100_000 else "") +
+                       (f" --epochs {args.epochs}" if args.epochs != 60 else ""),
+            "train_seed": TRAIN_SEED, "held_out_seed": HELD_SEED, "held_out_items": HELD_N,
+            "recipe": SP.training_recipe_id(TRAIN_SEED, n_tr), **rec}
+    json.dump(info, open(out[:-len(".fossur")] + ".json", "w"), indent=1)
+    say(f"model written to {out}")
+    line = {"metric": "surrogate training pipeline (labels + training + held-out error)",
+            "value": rec.get("label_seconds", 0.0) + tsec, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1e3 * (rec.get("label_seconds", 0.0) + tsec), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 MFMA / f32 walk", "data": "synthetic",
+            "config": {"workload": f"{n_tr} walk-labelled items x {rec['photons_each']} photons, 4 x MLP "
+                                   "8-256x4-3, 60 epochs"}, "model": info, "wall_s": time.perf_counter() - t_start}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def surrogate_main(args):
-    """Surrogate pipeline: walk-labelled training set (single layers, inputs
-    log-uniform over the workloads' optical depths, `train_photons` each),
-    4-member ensemble training, then a paint-design sweep (`designs` x
-    `lambdas`, one layer in air) run two ways -- plain Monte Carlo at
-    `fallback_photons` and surrogate + Monte Carlo fallback -- both verified
-    against 1e6-photon Monte Carlo on the surrogate's top designs and on
-    random designs."""
+    """The surrogate half of the metric as its own line (see surrogate_record),
+    with the FP64 oracle's network forward and Monte Carlo as CPU baseline."""
     t_start = time.perf_counter()
 
     def say(msg):
@@ -246,193 +501,50 @@ def surrogate_main(args):
     torch.cuda.set_device(0)
     ctx = fos.Context(0)
     h = ctx.handle
-    say("surrogate pipeline start")
-    rec_train = {}
-    if args.load_model:
-        fos.fos_sur_load(h, open(args.load_model, "rb").read())
-        say(f"model loaded from {args.load_model}")
-    else:
-        if args.load_data:
-            # stored labels, re-joined to features regenerated from the same item seeds
-            z = np.load(args.load_data)
-            if str(z["recipe"]) != SP.training_recipe_id(TRAIN_SEED):
-                raise SystemExit(f"{args.load_data}: labels were drawn by another training-item recipe")
-            n_tr, ph = int(z["n"]), int(z["photons"])
-            x, _, _, _ = SP.make_training_set(h, n_tr, ph, seed=TRAIN_SEED, label=False)
-            y = torch.from_numpy(z["y"]).cuda()
-            rec_train = {"samples": n_tr, "photons_each": ph, "label_seconds": float(z["label_seconds"]),
-                         "label_photon_steps": int(z["label_steps"]),
-                         "labels": f"loaded from {os.path.basename(args.load_data)}"}
-            say(f"training set loaded: {n_tr} samples")
-        else:
-            x, y, steps, secs = SP.make_training_set(h, args.train_samples, args.train_photons, seed=TRAIN_SEED,
-                                                     log=say)
-            rec_train = {"samples": args.train_samples, "photons_each": args.train_photons, "label_seconds": secs,
-                         "label_photon_steps": steps, "label_photon_steps_per_s": steps / secs}
-        if args.save_data:
-            _, yh0, _, _ = SP.make_training_set(h, HELD_N, args.train_photons, seed=HELD_SEED, chunk=HELD_N)
-            np.savez(args.save_data, y=y.cpu().numpy(), yh=yh0.cpu().numpy(), n=rec_train["samples"],
-                     recipe=SP.training_recipe_id(TRAIN_SEED),
-                     photons=rec_train["photons_each"], label_seconds=rec_train["label_seconds"],
-                     label_steps=rec_train["label_photon_steps"])
-            say(f"training and held-out labels written to {args.save_data}")
-        hist, tsec = SP.train(h, x, y, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_min=args.lr * 1e-2,
-                              seed=5)
-        rec_train.update({"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": tsec,
-                          "loss_first_epoch": hist[0].tolist(), "loss_last_epoch": hist[-1].tolist()})
-        say(f"trained {args.epochs} epochs in {tsec:.1f} s; mean loss {hist[0].mean():.4f} -> {hist[-1].mean():.4f}")
-        del x, y
-        if args.save_model:
-            open(args.save_model, "wb").write(fos.fos_sur_save(h))
-    # held-out set drawn like the training set
-    if args.load_data:
-        z = np.load(args.load_data)
-        xh, _, _, _ = SP.make_training_set(h, HELD_N, int(z["photons"]), seed=HELD_SEED, chunk=HELD_N, label=False)
-        yh = torch.from_numpy(z["yh"]).cuda()
-    else:
-        xh, yh, _, _ = SP.make_training_set(h, HELD_N, args.train_photons, seed=HELD_SEED, chunk=HELD_N)
-    rh, sh, ih = SP.predict(h, xh)
-    torch.cuda.synchronize()
-    eh = SP.errors(rh.cpu().numpy(), yh.cpu().numpy())
-    spread_h = sh.cpu().numpy()
-    rec_held = {"n": HELD_N, "error_vs_mc": eh, "frac_spread_gt_max": float((spread_h > args.spread_max).mean()),
-                "frac_in_domain": float(ih.float().mean().item())}
-    say(f"held-out error vs MC {eh}")
-
-    # the sweep: optics of every design on the GPU (log-normal size grid)
-    sweep = W.paint_sweep(args.designs, n_lambda=args.lambdas, photons=args.fallback_photons)
-    t0 = time.perf_counter()
-    prob = SP.paint_problem(h, sweep)
-    torch.cuda.synchronize()
-    t_optics = time.perf_counter() - t0
-    n = prob.n_items
-    D, L = args.designs, args.lambdas
-    say(f"sweep problem ready: {D} designs x {L} wavelengths ({t_optics:.2f} s of optics)")
-    # plain Monte Carlo at the fallback budget, on the first `mc_designs` designs
-    Dm = min(args.mc_designs, D)
-    sub = SP.take_items(prob, torch.arange(Dm * L, device="cuda"))
-    t0 = time.perf_counter()
-    _, steps_mc = SP.mc_fractions(h, sub, 424242)
-    torch.cuda.synchronize()
-    t_mc = time.perf_counter() - t0
-    del sub
-    say(f"plain Monte Carlo on {Dm} designs {t_mc:.2f} s")
-    rat_s = torch.zeros(3 * n, device="cuda")
-    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
-    spread = torch.zeros(n, device="cuda")
-    say("surrogate + fallback sweep: warm-up call")
-    fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515151, rat_s, used, spread=spread)
-    torch.cuda.synchronize()
-    say("surrogate + fallback sweep: timed call")
-    t0 = time.perf_counter()
-    n_fb = fos.fos_sweep_run(h, prob, args.spread_max, args.fallback_photons, 515152, rat_s, used, spread=spread)
-    torch.cuda.synchronize()
-    t_sur = time.perf_counter() - t0
-    n_spread = int((spread > args.spread_max).sum().item())
-    say(f"surrogate + fallback sweep {t_sur:.3f} s, {n_fb} of {n} items on Monte Carlo "
-        f"({n_spread} by spread, {n_fb - n_spread} outside the training box)")
-    # the fused inference kernel alone over every item (features already made),
-    # timed with events on the stream it runs on: the MFMA roofline
-    xs_all = torch.zeros(8 * n, device="cuda")
-    el_all = torch.zeros(n, dtype=torch.uint8, device="cuda")
-    fos.fos_sur_features(h, prob, xs_all, el_all)
-    pr_rat = torch.zeros(3 * n, device="cuda")
-    fos.fos_sur_predict(h, xs_all, eligible=el_all, rat=pr_rat)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    fos.fos_sur_predict(h, xs_all, eligible=el_all, rat=pr_rat)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_pred = ev0.elapsed_time(ev1) / 1e3
-    del xs_all, el_all, pr_rat
-    pred_flop = float(MLP_FORWARD_FLOP) * 4 * n
-    say(f"fused ensemble inference over {n} rows: {t_pred * 1e3:.1f} ms, {pred_flop / t_pred / 1e12:.1f} TFLOP/s")
-    # reductions: solar-weighted R (5778 K Planck stand-in) and 8-13 um emittance
-    lam = sweep.wavelengths
-    wr = torch.from_numpy(W.planck_weights(lam, 5778.0, 0.3, 2.5).astype(np.float32)).cuda()
-    we = torch.from_numpy(W.planck_weights(lam, 300.0, 8.0, 13.0).astype(np.float32)).cuda()
-    red_s = torch.zeros(2 * D, device="cuda")
-    fos.fos_spectral_reduce(h, D, L, rat_s, wr, we, red_s)
-    fom = red_s.view(D, 2).sum(1).cpu().numpy()
-    K = min(args.verify_designs, D)
-    top = np.argsort(-fom)[:K]
-    rnd = np.random.default_rng(3).choice(D, size=K, replace=False)
-    ver = {}
-    for name, designs in ((("top", top), ("random", rnd)) if K > 0 else ()):
-        items = torch.from_numpy((designs[:, None] * L + np.arange(L)[None, :]).ravel()).cuda()
-        vprob = SP.take_items(prob, items)
-        ref, _ = SP.mc_fractions(h, SP.with_photons(vprob, 1_000_000), 99 + len(ver))
-        plain, _ = SP.mc_fractions(h, SP.with_photons(vprob, args.fallback_photons), 77 + len(ver))
-        torch.cuda.synchronize()
-        refn = ref.cpu().numpy()
-        ver[name] = {"designs": int(K),
-                     "surrogate_sweep_vs_1e6_mc": SP.errors(rat_s.view(n, 3)[items].cpu().numpy().ravel(), refn),
-                     "plain_mc_vs_1e6_mc": SP.errors(plain.cpu().numpy(), refn),
-                     "fallback_frac": float(used[items].float().mean().item())}
-        say(f"verified {name} {K} designs: {ver[name]}")
-    # CPU oracle baseline: plain FP64 Monte Carlo on the first designs and the
-    # FP64 network forward of the trained ensemble on 1e4 of the sweep's rows
+    sub = surrogate_record(h, args, say)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         from oracle import mlp as omlp
         threads = oracle.default_threads()
-        Dc = 2
-        T = {k: v[: Dc * L].cpu().numpy() for k, v in prob.tensors.items() if k != "photons"}
+        L, fb = args.lambdas, args.fallback_photons
+        sweep = W.paint_sweep(2, n_lambda=L, photons=fb)
+        prob = SP.paint_problem(h, sweep)
+        T = {k: v.cpu().numpy() for k, v in prob.tensors.items() if k != "photons"}
         f64 = lambda k: T[k].astype(np.float64)
         t0 = time.perf_counter()
         o = oracle.walk_batch(T["n_layers"], f64("mu_s"), f64("mu_a"), f64("g"), f64("n_layer"), f64("thickness"),
                               f64("n_upper"), f64("n_lower"), f64("k_lower"), f64("mu0"),
-                              np.full(Dc * L, args.fallback_photons, np.uint64), seed=0x0C9B, n_threads=threads)
+                              np.full(2 * L, fb, np.uint64), seed=0x0C9B, n_threads=threads)
         dt_mc = time.perf_counter() - t0
         stats, params, _ = fos.parse_sur_blob(fos.fos_sur_save(h))
-        rows = 10_000
-        xr = torch.zeros(8 * rows, device="cuda")
-        fos.fos_sur_features(h, SP.take_items(prob, torch.arange(rows, device="cuda")), xr)
-        xh64 = xr.view(rows, 8).cpu().numpy().astype(np.float64)
-        xs64 = (xh64 - stats[0].astype(np.float64)) * stats[1].astype(np.float64)
+        x = torch.zeros(8 * 2 * L, device="cuda")
+        fos.fos_sur_features(h, prob, x)
+        xs64 = (x.view(2 * L, 8).cpu().numpy().astype(np.float64) - stats[0]) * stats[1]
+        rows = np.tile(xs64, (25, 1))
         sizes = (8, 256, 256, 256, 256, 3)
         t0 = time.perf_counter()
         for m in range(4):
             v, layers, off = params[m].astype(np.float64), [], 0
             for k_in, k_out in zip(sizes[:-1], sizes[1:]):
-                layers.append((v[off:off + k_in * k_out].reshape(k_in, k_out), v[off + k_in * k_out:off + k_in * k_out + k_out]))
+                layers.append((v[off:off + k_in * k_out].reshape(k_in, k_out),
+                               v[off + k_in * k_out:off + k_in * k_out + k_out]))
                 off += k_in * k_out + k_out
-            omlp.forward(layers, xs64)
+            omlp.forward(layers, rows)
         dt_nn = time.perf_counter() - t0
-        cpu = {"value": Dc / dt_mc, "unit": "spectra/s", "cores": threads, "kind": "oracle",
-               "sample": f"plain FP64 Monte Carlo of {Dc} designs x {L} wavelengths at {args.fallback_photons} "
-                         f"photons ({dt_mc:.1f} s, {float(o[:, 5].sum()):.3e} photon-steps)",
-               "mlp_forward_rows_per_s": rows / dt_nn,
-               "mlp_sample": f"FP64 forward of the 4 trained members on {rows} sweep rows ({dt_nn:.2f} s, numpy)",
+        cpu = {"value": 2 / dt_mc, "unit": "spectra/s", "cores": threads, "kind": "oracle",
+               "sample": f"plain FP64 Monte Carlo of 2 designs x {L} wavelengths at {fb} photons ({dt_mc:.1f} s, "
+                         f"{float(o[:, 5].sum()):.3e} photon-steps)",
+               "mlp_forward_rows_per_s": len(rows) / dt_nn,
+               "mlp_sample": f"FP64 forward of the 4 members on {len(rows)} rows ({dt_nn:.2f} s, numpy)",
                "cpu": _cpu_model()}
         say(f"cpu baseline: {cpu}")
-    sps_sur = D / t_sur
-    sps_mc = Dm / t_mc
-    rec = {
-        "metric": "spectra/s: surrogate + Monte Carlo fallback vs plain GPU Monte Carlo (<=0.01 R/A/T error)",
-        "value": sps_sur, "unit": "spectra/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": 1e3 * t_sur, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 MFMA / f32 walk", "data": "synthetic",
-        "config": {"workload": f"paint sweep: {D} single-layer designs x {L} wavelengths (0.3-16 um), "
-                               f"spread gate {args.spread_max}, fallback {args.fallback_photons} photons",
-                   "items": n},
-        "optics_seconds": t_optics,
-        "plain_mc_spectra_per_s": sps_mc, "plain_mc_seconds": t_mc, "plain_mc_designs": Dm,
-        "plain_mc_photon_steps": steps_mc,
-        "speedup_vs_plain_mc_at_fallback_photons": sps_sur / sps_mc,
-        "speedup_vs_plain_mc_scaled": {"1e4": sps_sur / (sps_mc * args.fallback_photons / 1e4),
-                                       "1e5": sps_sur / (sps_mc * args.fallback_photons / 1e5),
-                                       "1e6": sps_sur / (sps_mc * args.fallback_photons / 1e6)},
-        "roofline": {"bound": "mfma", "achieved": pred_flop / t_pred / 1e12, "peak": BF16_MFMA_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": pred_flop / t_pred / BF16_MFMA_PEAK, "traffic": None,
-                     "kernel": "fos::mlp_infer_kernel", "rows": n, "kernel_ms": 1e3 * t_pred,
-                     "work_per_row_flop": 4 * MLP_FORWARD_FLOP},
-        "cpu_baseline": cpu,
-        "fallback_rate": n_fb / n, "fallback_by_spread": n_spread, "fallback_out_of_domain": n_fb - n_spread,
-        "training": rec_train, "held_out": rec_held, "verification": ver,
-        "wall_s": time.perf_counter() - t_start,
-    }
+    rec = {"metric": sub["metric"], "value": sub["value"], "unit": "spectra/s", "n_gpus": 1, "steps": 2,
+           "warmup": 1, "ms_per_step": 1e3 * sub["seconds"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16 MFMA / f32 walk", "data": "synthetic", "config": sub["config"],
+           "roofline": dict(sub["inference_roofline"], traffic=None), "cpu_baseline": cpu,
+           **{k: v for k, v in sub.items() if k not in ("metric", "value", "unit", "config", "inference_roofline")},
+           "wall_s": time.perf_counter() - t_start}
     ctx.close()
     print(json.dumps(rec), flush=True)
     return 0
@@ -701,9 +813,12 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
     ap.add_argument("--workload", default="two_species_500",
-                    choices=["two_species_500", "stacks_3layer", "surrogate", "paper_context", "weighted", "optics"],
-                    help="two_species_500 (default, the headline line), stacks_3layer (batched sweep), "
-                         "surrogate (training on walk labels + design sweep with Monte Carlo fallback) or "
+                    choices=["two_species_500", "stacks_3layer", "surrogate", "surrogate_train", "paper_context",
+                             "weighted", "optics"],
+                    help="two_species_500 (default, the headline line; with the surrogate sweep as a sub-record), "
+                         "stacks_3layer (batched sweep), surrogate (the committed ensemble: design sweep with Monte "
+                         "Carlo fallback against plain Monte Carlo), surrogate_train (walk labels + training + "
+                         "held-out error; writes the model) or "
                          "paper_context (a run shaped like the paper's desktop timing, GPU and oracle) or "
                          "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency) or "
                          "optics (per-entry GPU Mie + effective medium: homogeneous, coated, spread)")
@@ -713,15 +828,22 @@ def main(argv=None):
     ap.add_argument("--lambdas", type=int, default=200)
     ap.add_argument("--spread-max", type=float, default=0.01)
     ap.add_argument("--fallback-photons", type=int, default=100_000)
-    ap.add_argument("--verify-designs", type=int, default=20)
+    ap.add_argument("--verify-designs", type=int, default=1000,
+                    help="top and random designs of the sweep verified at 1e6 photons")
+    ap.add_argument("--designs-sweep", type=int, default=1_000_000, help="designs of the surrogate paint sweep")
     ap.add_argument("--mc-designs", type=int, default=4096,
                     help="designs of the sweep timed with plain Monte Carlo (the first ones)")
+    ap.add_argument("--no-surrogate", action="store_true", help="leave the surrogate sub-record out")
+    ap.add_argument("--tail-lanes", type=int, default=16,
+                    help="label walks: tail_lanes launch knob (0 = the context default)")
+    ap.add_argument("--label-state", default="", help="surrogate_train: resumable label state (.npz)")
+    ap.add_argument("--label-launches", default="", help="surrogate_train: walk only launches a:b of the labels")
     ap.add_argument("--save-data", default="", help="write the walk-labelled training and held-out sets (.npz)")
     ap.add_argument("--load-data", default="", help="read training and held-out sets written by --save-data")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=2048)
-    ap.add_argument("--save-model", default="")
-    ap.add_argument("--load-model", default="")
+    ap.add_argument("--save-model", default="", help="surrogate_train: model path (default: the committed one)")
+    ap.add_argument("--model", default=MODEL_PATH, help="surrogate sweep: the ensemble to load (.fossur)")
     ap.add_argument("--designs", type=int, default=4096, help="designs of the stacks_3layer sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration under rocprofv3)")
@@ -733,6 +855,8 @@ def main(argv=None):
         return 2
     if args.workload == "surrogate":
         return surrogate_main(args)
+    if args.workload == "surrogate_train":
+        return surrogate_train_main(args)
     if args.workload == "stacks_3layer":
         return sweep_main(args)
     if args.workload == "paper_context":
@@ -827,6 +951,14 @@ def main(argv=None):
         host = [o.cpu().numpy() for o in optics]
         rec["cpu_baseline"] = cpu_baseline(wl, host, args.cpu_seconds)
         rec["gpu_over_cpu"] = rec["value"] / rec["cpu_baseline"]["value"]
+    if not args.no_surrogate:
+        # the metric's second half: surrogate + Monte Carlo fallback against
+        # plain GPU Monte Carlo on the paint sweep, with the committed model
+        del prob, optics, tallies, warm
+        torch.cuda.empty_cache()
+        t_sub = time.perf_counter()
+        say = lambda m: print(f"[bench] {m} ({time.perf_counter() - t_sub:.1f} s)", file=sys.stderr, flush=True)
+        rec["surrogate"] = surrogate_record(h, args, say)
     ctx.close()
     print(json.dumps(rec), flush=True)
     return 0

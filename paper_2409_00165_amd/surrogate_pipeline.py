@@ -92,52 +92,90 @@ def with_photons(prob, photons: int):
     return fos.MCProblem(**T)
 
 
-def mc_fractions(ctx, prob, seed: int):
-    """Run the walk on every item; returns (rat [n*3] device, photon-steps)."""
+def mc_fractions(ctx, prob, seed: int, launch=None, stream=None):
+    """Run the walk on every item; returns (rat [n*3] device, photon-steps,
+    capped photons, largest capped fraction of an item)."""
     import torch
     n = prob.n_items
     tal = torch.zeros(n * fos.N_TALLY, dtype=torch.int64, device="cuda")
-    fos.fos_mc_run(ctx, prob, seed, tal)
+    fos.fos_mc_run(ctx, prob, seed, tal, launch=launch, stream=stream)
     rat = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
-    fos.fos_mc_fractions(ctx, tal, rat)
-    steps = int(tal.view(n, fos.N_TALLY)[:, 5].sum().item())
-    return rat, steps
+    fos.fos_mc_fractions(ctx, tal, rat, stream=stream)
+    t = tal.view(n, fos.N_TALLY)
+    photons = t[:, :5].sum(1).clamp(min=1).double()
+    capped_frac = float((t[:, 4].double() / photons).max().item()) if n else 0.0
+    return rat, int(t[:, 5].sum().item()), int(t[:, 4].sum().item()), capped_frac
 
 
-def training_recipe_id(seed: int) -> str:
+def training_recipe_id(seed: int, n: int) -> str:
     """Fingerprint of the training-item recipe (the first 1000 items drawn
-    from `seed`): stored with saved labels, so labels are never re-joined to
-    features drawn by a different recipe."""
+    from `seed`) and of the labelling order and launches of n items: stored
+    with saved labels, so labels are never re-joined to features drawn or
+    walked by a different recipe."""
     import hashlib
     a = W.surrogate_training_items(1000, seed)
     h = hashlib.sha1()
     for k in sorted(a):
         h.update(np.ascontiguousarray(a[k]).tobytes())
+    h.update(np.ascontiguousarray(_walk_cost(a)).tobytes())
+    h.update(repr(label_launch_sizes(n)).encode())
     return h.hexdigest()[:16]
 
 
 def _walk_cost(a):
-    """Ordering key for the labelling walks of single-layer items: the length
-    of their longest walks, about the diffusion time (tau_s (1 - g))^2 of the
-    slab, or the scatterings before absorption (tau_s / tau_a) if fewer."""
+    """Ordering key for the labelling walks of single-layer items: the
+    number of scatterings of their longest walks.  A photon that diffuses
+    across a slab of scattering depth tau_s needs about (tau_s (1 - g))^2
+    transport mean free paths of 1 / (1 - g) scatterings each, i.e. about
+    tau_s^2 (1 - g) scatterings; absorption ends a walk after about
+    tau_s / tau_a of them, whichever comes first; at least one."""
     t = a["thickness"][:, 0]
     tau_s, tau_a = a["mu_s"][:, 0] * t, a["mu_a"][:, 0] * t
-    red = tau_s * (1.0 - a["g"][:, 0])
-    return np.minimum(tau_s / np.maximum(tau_a, 1e-12), np.maximum(red, 1.0) ** 2)
+    diffusion = np.maximum(tau_s * tau_s * (1.0 - a["g"][:, 0]), 1.0)
+    return np.minimum(tau_s / np.maximum(tau_a, 1e-12), diffusion)
 
 
-def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True):
+def label_launch_sizes(n: int, first: int = 1024, largest: int = 262_144):
+    """Items per labelling launch, longest walks first: two launches of
+    `first` items, then sizes doubling every two launches up to `largest`.
+    The thick items, whose walks hold most of the photon-steps, run in short
+    launches; the light bulk runs in large ones."""
+    sizes, size, done = [], first, 0
+    while done < n:
+        for _ in range(2):
+            m = min(size, n - done)
+            if m > 0:
+                sizes.append(m)
+                done += m
+        size = min(2 * size, largest)
+    return sizes
+
+
+# photons of an item that the per-photon step cap may stop before the labels
+# are rejected (a capped photon is counted in no outcome)
+MAX_CAPPED_FRACTION = 1e-3
+
+
+def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True,
+                      launch=None, launch_sizes=None, launches=None, y=None, on_launch=None):
     """n single-layer items labelled by the walk at `photons` each.
     Returns (x [n*8], y [n*3], photon-steps, seconds).  With label=False only
     the features are made (y is None): the items are a function of
     (n, seed, chunk), so stored labels can be re-joined to their features.
 
-    The walks take the items in launches of `chunk`, ordered by _walk_cost,
-    longest first.  A few photons of the thick, weakly absorbing items walk
-    10^7..10^8 steps on one lane and a launch lasts as long as its longest
-    photon: gathered in the first launch they run side by side, and the
-    launches after it hold short walks only.  Labels depend on
-    (n, seed, chunk)."""
+    The items are ordered by _walk_cost, longest first, and walked in the
+    launches of `launch_sizes` (default label_launch_sizes(n)), launch c
+    under seed + c.  Two
+    contexts take turns, each launch on its own stream, so a launch starts
+    on the CUs that the one before it frees while its last long walks run;
+    a launch waits only for the one two back.  Labels depend on (n, seed,
+    chunk) and on that order and those sizes.  A label whose item had more
+    than MAX_CAPPED_FRACTION of its photons stopped by the step cap raises.
+
+    `launches` (a range of launch indices, default all) walks only those
+    launches, writing their rows of `y` (a device tensor [n*3] to continue,
+    or None for a new one); `on_launch(c, steps, capped)` is called as each
+    launch completes, so a long labelling can be resumed."""
     import torch
     t0 = time.perf_counter()
     parts, xs = [], []
@@ -154,18 +192,64 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
         return x, None, 0, time.perf_counter() - t0
     items = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
     order = np.argsort(-_walk_cost(items), kind="stable")
-    y = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
-    steps = 0
-    for c, b in enumerate(range(0, n, chunk)):
-        idx = order[b:b + chunk]
-        m = len(idx)
-        rat, s = mc_fractions(ctx, device_problem({k: v[idx] for k, v in items.items()}), seed + c)
-        y.view(n, 3)[torch.from_numpy(idx).cuda()] = rat.view(m, 3)
-        steps += s
-        if log:
-            log(f"training labels {b + m}/{n} ({time.perf_counter() - t0:.1f} s, {steps:.3e} photon-steps)")
+    if y is None:
+        y = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    return x, y, steps, time.perf_counter() - t0
+    ctx2 = fos.Context(0)
+    ctxs = (ctx, ctx2.handle)
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    totals = {"steps": 0, "capped": 0, "worst_capped": 0.0}
+    pending = []
+
+    def finish(job):
+        c, idx, tal, done, _prob = job
+        done.synchronize()
+        m = len(idx)
+        t = tal.view(m, fos.N_TALLY)
+        rat = torch.zeros(m * 3, dtype=torch.float32, device="cuda")
+        fos.fos_mc_fractions(ctxs[c % 2], tal, rat)
+        y.view(n, 3)[torch.from_numpy(idx).cuda()] = rat.view(m, 3)
+        steps, capped = int(t[:, 5].sum().item()), int(t[:, 4].sum().item())
+        worst = float((t[:, 4].double() / photons).max().item())
+        totals["steps"] += steps
+        totals["capped"] += capped
+        totals["worst_capped"] = max(totals["worst_capped"], worst)
+        if log:
+            log(f"training labels: launch {c} ({m} items) done, {steps:.3e} photon-steps, {capped} capped photons "
+                f"(item worst {worst:.1e}), {time.perf_counter() - t0:.1f} s")
+        if worst > MAX_CAPPED_FRACTION:
+            raise RuntimeError(f"labelling launch {c}: an item had {worst:.2e} of its photons stopped by the "
+                               f"step cap (more than {MAX_CAPPED_FRACTION})")
+        if on_launch:
+            on_launch(c, steps, capped)
+
+    try:
+        sizes = list(launch_sizes) if launch_sizes is not None else label_launch_sizes(n)
+        if sum(sizes) != n or min(sizes) < 1:
+            raise ValueError("launch sizes must be positive and add up to n")
+        todo = range(len(sizes)) if launches is None else launches
+        starts = np.concatenate([[0], np.cumsum(sizes)])
+        for c in todo:
+            if len(pending) == 2:
+                finish(pending.pop(0))
+            m = sizes[c]
+            idx = order[starts[c]:starts[c] + m]
+            st = streams[c % 2]
+            with torch.cuda.stream(st):
+                prob = device_problem({k: v[idx] for k, v in items.items()})
+                tal = torch.zeros(m * fos.N_TALLY, dtype=torch.int64, device="cuda")
+                fos.fos_mc_run(ctxs[c % 2], prob, seed + c, tal, launch=launch, stream=st)
+                done = torch.cuda.Event()
+                done.record(st)
+            pending.append((c, idx, tal, done, prob))
+            if log:
+                log(f"training labels: launch {c} ({m} items) started")
+        while pending:
+            finish(pending.pop(0))
+    finally:
+        torch.cuda.synchronize()
+        ctx2.close()
+    return x, y, totals["steps"], time.perf_counter() - t0
 
 
 def train(ctx, x, y, epochs=30, batch=8192, lr=1e-3, lr_min=1e-5, seed=1):
@@ -185,6 +269,17 @@ def predict(ctx, x):
     ind = torch.zeros(n, dtype=torch.uint8, device="cuda")
     fos.fos_sur_predict(ctx, x, rat=rat, spread=spread, in_domain=ind)
     return rat, spread, ind
+
+
+def weights_only_blob(blob: bytes) -> bytes:
+    """A fos_sur_save blob without the optimiser state: the header with its
+    has-optimiser word cleared, the feature statistics and the weights."""
+    import struct
+    if blob[:8] != b"FOSSUR01":
+        raise ValueError("not a surrogate blob")
+    members, features, hidden, params, _has_opt, _step = struct.unpack("<6I", blob[8:32])
+    body = blob[32:32 + 128 + 4 * members * params]
+    return blob[:8] + struct.pack("<6I", members, features, hidden, params, 0, 0) + body
 
 
 def errors(a, b):

@@ -322,6 +322,27 @@ def paint_sweep(n_designs: int, n_lambda: int = 200, seed: int = 20240901, photo
     return PaintSweep(grid_log(0.3, 16.0, n_lambda), sp, mat, rmed, f, t, photons)
 
 
+def paint_unsnapped(designs, n_designs: int, n_lambda: int = 200, seed: int = 20240901,
+                    photons: int = 100_000) -> Workload:
+    """The designs `designs` (indices) of paint_sweep(n_designs, ...) with
+    their median radius and matrix index as drawn, before the snapping to
+    the grids: the same draws, continuous values, as a Workload whose
+    optics go through the per-entry path."""
+    rng = np.random.default_rng(seed)
+    n = n_designs
+    t = rng.uniform(5.0, 500.0, n)
+    f = rng.uniform(0.01, 0.3, n)
+    rm = rng.uniform(0.05, 1.0, n)
+    sp = (rng.uniform(size=n) >= 0.5).astype(np.int32)
+    nm = rng.uniform(1.3, 1.7, n)
+    out = []
+    for d in designs:
+        r, w = lognormal_bins(float(rm[d]), PAINT_SIGMA_LN, PAINT_BINS)
+        pop = Particles(PAINT_SPECIES[int(sp[d])], r, float(f[d]) * w)
+        out.append(Design([Layer(float(t[d]), float(nm[d]), PAINT_KM, [pop])], photons=photons))
+    return Workload("paint_unsnapped", grid_log(0.3, 16.0, n_lambda), out)
+
+
 def paint_1layer(n_designs: int, n_lambda: int = 200, seed: int = 20240901,
                  photons: int = 100_000) -> Workload:
     """Single-layer paint designs in air (the surrogate's domain) as a

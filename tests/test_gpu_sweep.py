@@ -68,7 +68,7 @@ def test_sweep_all_fallback_equals_plain_monte_carlo(trained, torch):
     rat = torch.zeros(3 * n, device="cuda")
     used = torch.zeros(n, dtype=torch.uint8, device="cuda")
     nf = fos.fos_sweep_run(h, prob, 0.0, 20_000, 77, rat, used)       # spread > 0 always -> all MC
-    ref, _ = SP.mc_fractions(h, SP.with_photons(prob, 20_000), 77)
+    ref = SP.mc_fractions(h, SP.with_photons(prob, 20_000), 77)[0]
     torch.cuda.synchronize()
     assert nf == n and bool((used == 1).all())
     assert torch.equal(rat, ref)
@@ -148,8 +148,9 @@ def test_trained_surrogate_tracks_monte_carlo(trained, torch):
 
 
 def test_training_labels_follow_their_items_across_launches(torch):
-    """make_training_set walks the items longest first, in several launches,
-    and puts each label back on its item.  Each item is walked once more on
+    """make_training_set walks the items longest first, in several launches
+    (two contexts taking turns on two streams), and puts each label back on
+    its item.  Each item is walked once more on
     its own seed, in recipe order: the two estimates agree within 5 binomial
     standard errors item by item (a label on the wrong item would be far off),
     and the features are those of label=False."""
@@ -159,13 +160,13 @@ def test_training_labels_follow_their_items_across_launches(torch):
     c = fos.Context(0)
     h = c.handle
     n, ph, chunk = 3000, 2000, 1000
-    x, y, steps, _ = SP.make_training_set(h, n, ph, seed=77, chunk=chunk)
+    x, y, steps, _ = SP.make_training_set(h, n, ph, seed=77, chunk=chunk, launch_sizes=[500, 500, 800, 1200])
     x2, _, _, _ = SP.make_training_set(h, n, ph, seed=77, chunk=chunk, label=False)
     assert torch.equal(x, x2) and steps > 0
     parts = [W.surrogate_training_items(min(chunk, n - b), 77 + 7919 * k, photons=ph)
              for k, b in enumerate(range(0, n, chunk))]
     items = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
-    again, _ = SP.mc_fractions(h, SP.device_problem(items), 4242)
+    again = SP.mc_fractions(h, SP.device_problem(items), 4242)[0]
     torch.cuda.synchronize()
     a = y.view(n, 3).cpu().numpy().astype(np.float64)
     b = again.view(n, 3).cpu().numpy().astype(np.float64)

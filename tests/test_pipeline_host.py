@@ -13,9 +13,19 @@ def _items(tau_s, tau_a, g, t=100.0):
 
 
 def test_walk_cost_is_diffusion_time_or_scatterings_before_absorption():
-    # thick and lossless: (tau_s (1 - g))^2; strongly absorbing: tau_s / tau_a; thin: at least 1
+    # thick and lossless: tau_s^2 (1 - g) scatterings, i.e. (tau_s (1 - g))^2
+    # transport paths of 1 / (1 - g) scatterings; strongly absorbing:
+    # tau_s / tau_a; thin: at least 1
     c = SP._walk_cost(_items([1e4, 1e4, 1e4, 0.1], [1e-4, 10.0, 1e-4, 1e-4], [0.0, 0.0, 0.9, 0.0]))
-    assert np.allclose(c, [1e8, 1e3, 1e6, 1.0])
+    assert np.allclose(c, [1e8, 1e3, 1e7, 1.0])
+
+
+def test_label_launch_sizes_cover_the_items_longest_first():
+    sizes = SP.label_launch_sizes(2_000_000)
+    assert sum(sizes) == 2_000_000 and sizes[:4] == [1024, 1024, 2048, 2048]
+    assert max(sizes) == 262_144 and all(s > 0 for s in sizes)
+    assert SP.label_launch_sizes(3000) == [1024, 1024, 952]
+    assert sum(SP.label_launch_sizes(20_000)) == 20_000
 
 
 def test_walk_cost_orders_the_training_recipe_longest_first():

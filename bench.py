@@ -226,22 +226,6 @@ HELD_SEED = 777           # held-out items
 HELD_N = 10_000
 INIT_SEED = 5             # He initialisation and shuffles of the ensemble
 MODEL_PATH = os.path.join(ROOT, "paper_2409_00165_amd", "trained", "surrogate_ens4.fossur")
-MODEL_INFO = MODEL_PATH[:-len(".fossur")] + ".json"
-
-
-def load_model(h, path=MODEL_PATH):
-    """Load an ensemble written by surrogate_train (by default the committed
-    one) after checking its bytes against the digest recorded beside it;
-    returns its provenance record."""
-    import hashlib
-    from paper_2409_00165_amd import fos
-    blob = open(path, "rb").read()
-    info_path = path[:-len(".fossur")] + ".json"
-    info = json.load(open(info_path))
-    if hashlib.sha256(blob).hexdigest() != info["sha256"]:
-        raise SystemExit(f"{path} does not match the digest in {info_path}")
-    fos.fos_sur_load(h, blob)
-    return info
 
 
 def surrogate_record(h, args, say):
@@ -256,7 +240,7 @@ def surrogate_record(h, args, say):
     from paper_2409_00165_amd import fos
     from paper_2409_00165_amd import surrogate_pipeline as SP
     from paper_2409_00165_amd import workloads as W
-    info = load_model(h, args.model)
+    info = SP.load_model(h, args.model)
     say(f"surrogate: model {os.path.basename(args.model)} ({info['sha256'][:12]}) loaded")
     D, L, fb = args.designs_sweep, args.lambdas, args.fallback_photons
     sweep = W.paint_sweep(D, n_lambda=L, photons=fb)

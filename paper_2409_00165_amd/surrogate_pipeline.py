@@ -7,6 +7,7 @@ orchestrates the calls and moves device tensors around.
 """
 from __future__ import annotations
 
+import os
 import time
 
 import numpy as np
@@ -269,6 +270,26 @@ def predict(ctx, x):
     ind = torch.zeros(n, dtype=torch.uint8, device="cuda")
     fos.fos_sur_predict(ctx, x, rat=rat, spread=spread, in_domain=ind)
     return rat, spread, ind
+
+
+# the committed ensemble (written by `bench.py --workload surrogate_train`)
+# and its provenance record beside it
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "trained", "surrogate_ens4.fossur")
+
+
+def load_model(ctx, path: str = MODEL_PATH) -> dict:
+    """Load an ensemble written by the training leg (by default the committed
+    one) after checking its bytes against the sha256 recorded in the .json
+    beside it; returns that provenance record."""
+    import hashlib
+    import json
+    blob = open(path, "rb").read()
+    info_path = path[:-len(".fossur")] + ".json"
+    info = json.load(open(info_path))
+    if hashlib.sha256(blob).hexdigest() != info["sha256"]:
+        raise ValueError(f"{path} does not match the digest in {info_path}")
+    fos.fos_sur_load(ctx, blob)
+    return info
 
 
 def weights_only_blob(blob: bytes) -> bytes:

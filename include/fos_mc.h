@@ -158,6 +158,26 @@ fos_status fos_mc_execute(fos_ctx* ctx, uint64_t seed, const fos_mc_launch* laun
 fos_status fos_mc_run(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
                       const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
 
+/* Allocation-free fos_mc_run, for callers that cannot allocate device or
+ * pinned memory at call time (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same problem, seed, launch,
+ * tallies and results as fos_mc_run -- bit for bit -- but the packed item
+ * table, the work queue and the validation words live in a fixed device
+ * array of FOS_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is
+ * loaded, instead of the context's scratch; the context's prepared problem
+ * is left as it was.  A problem needing more than that (256 B + its packed
+ * table, 32 B per item plus 64 B per layer slot, rounded up to 256 B, + 8 B
+ * per item + 8 B) is rejected with FOS_E_INVALID_ARG before any work is
+ * enqueued: about 160,000 single-layer or 30,000 eight-layer items.  Every
+ * call on one GPU uses that GPU's one array and leaves it holding its table:
+ * calls that overlap on one GPU (other threads, other contexts, or another
+ * stream before this call's walk has finished) race and give wrong tallies.
+ * Validation synchronises `hip_stream` once, as fos_mc_prepare does; the
+ * walk is then asynchronous on it. */
+#define FOS_NOALLOC_SCRATCH_BYTES (16u << 20)
+fos_status fos_mc_run_noalloc(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
+                              const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
+
 /* Launch tuning for the prepared problem: walks at most `photon_cap`
  * photons of every item (0 = all) under a coordinate search over
  * refill_min x chunk x block_size x blocks_per_cu, times each candidate with

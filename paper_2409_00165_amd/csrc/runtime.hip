@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,15 +66,20 @@ fos_status check_launch(fos_ctx* c, const fos_mc_launch& L)
 constexpr int32_t kAutoChunkMin = 256;
 constexpr int32_t kAutoChunkMax = 2048;
 
-int32_t auto_chunk(const fos_ctx* c, const fos_mc_launch& L)
+int32_t auto_chunk_for(int n_cu, int32_t n_items, uint64_t max_photons, const fos_mc_launch& L)
 {
-    const uint64_t n = (uint64_t)std::max(c->n_items, 1);
-    const uint64_t bound = c->max_photons > UINT64_MAX / n ? UINT64_MAX : c->max_photons * n;
-    const uint64_t waves = (uint64_t)c->n_cu * (uint64_t)L.blocks_per_cu * (uint64_t)(L.block_size / 64);
+    const uint64_t n = (uint64_t)std::max(n_items, 1);
+    const uint64_t bound = max_photons > UINT64_MAX / n ? UINT64_MAX : max_photons * n;
+    const uint64_t waves = (uint64_t)n_cu * (uint64_t)L.blocks_per_cu * (uint64_t)(L.block_size / 64);
     const uint64_t per = bound / (4 * std::max<uint64_t>(waves, 1));
     int32_t chunk = kAutoChunkMax;
     while (chunk > kAutoChunkMin && (uint64_t)chunk > per) chunk /= 2;
     return chunk;
+}
+
+int32_t auto_chunk(const fos_ctx* c, const fos_mc_launch& L)
+{
+    return auto_chunk_for(c->n_cu, c->n_items, c->max_photons, L);
 }
 
 fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
@@ -99,6 +105,41 @@ fos_mc_launch resolve(const fos_ctx* c, const fos_mc_launch* o)
     if (!(o && o->chunk) && !c->chunk_set) r.chunk = auto_chunk(c, r);
     return r;
 }
+
+// Scratch of the allocation-free walk (fos_mc_run_noalloc): the packed item
+// table, the chunk prefix and the status and queue words live in this
+// file-scope device array instead of context allocations.  Each device that
+// loads the library holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives for that
+// device (kept per device below), never through the array's name.
+constexpr size_t kNoAllocWordsBytes = 256;   // [0] validation verdict, [1] largest budget, [2] chunk counter
+static __device__ __align__(256) unsigned char scratch[FOS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// With `device` current: the device address of its copy of `scratch`, taken
+// once per device.
+hipError_t scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch[device] = static_cast<unsigned char*>(p);
+    return e;
+}
+
+unsigned char* scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -148,6 +189,10 @@ fos_status fos_create(int hip_device, fos_ctx** out)
         hipHostMalloc(reinterpret_cast<void**>(&c->err_host), sizeof(unsigned long long)) != hipSuccess) {
         fos_destroy(c);
         return FOS_E_OUT_OF_MEMORY;
+    }
+    if (scratch_init(hip_device) != hipSuccess) {
+        fos_destroy(c);
+        return FOS_E_DEVICE;
     }
     *out = c;
     return FOS_OK;
@@ -496,6 +541,93 @@ fos_status fos_mc_run(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const 
     fos_status s = fos_mc_prepare(c, p, hip_stream);
     if (s != FOS_OK) return s;
     return fos_mc_execute(c, seed, launch, tallies, hip_stream);
+}
+
+fos_status fos_mc_run_noalloc(fos_ctx* c, const fos_mc_problem* p, uint64_t seed, const fos_mc_launch* launch,
+                              uint64_t* tallies, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (!p) return fail(c, FOS_E_INVALID_ARG, "problem is NULL");
+    if (p->n_items < 0) return fail(c, FOS_E_INVALID_ARG, "n_items must be >= 0");
+    if (p->max_layers < 1 || p->max_layers > FOS_MAX_LAYERS)
+        return fail(c, FOS_E_INVALID_ARG, "max_layers must be in [1, FOS_MAX_LAYERS]");
+    if (launch) {
+        const fos_mc_launch L = merge(c->defaults, launch);
+        fos_status s = check_launch(c, L);
+        if (s != FOS_OK) return s;
+    }
+    if (p->n_items == 0) return FOS_OK;
+    if (!p->n_layers || !p->mu_s || !p->mu_a || !p->g || !p->n_layer || !p->thickness || !p->n_upper ||
+        !p->n_lower || !p->k_lower || !p->mu0 || !p->photons)
+        return fail(c, FOS_E_INVALID_ARG, "a problem array pointer is NULL");
+    if (!tallies) return fail(c, FOS_E_INVALID_ARG, "tallies is NULL");
+    const int rf = fos::rec_f4(p->max_layers);
+    const size_t table_bytes = round256((size_t)p->n_items * rf * sizeof(float4));
+    const size_t need = kNoAllocWordsBytes + table_bytes + ((size_t)p->n_items + 1) * sizeof(unsigned long long);
+    if (need > FOS_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "problem needs %zu bytes of scratch; fos_mc_run_noalloc holds %zu",
+                      need, (size_t)FOS_NOALLOC_SCRATCH_BYTES);
+        return fail(c, FOS_E_INVALID_ARG, buf);
+    }
+    unsigned char* base = scratch_of(c->device);
+    if (!base) return fail(c, FOS_E_DEVICE, "scratch address of the device unknown");
+    unsigned long long* words = reinterpret_cast<unsigned long long*>(base);
+    float4* table = reinterpret_cast<float4*>(base + kNoAllocWordsBytes);
+    unsigned long long* prefix = reinterpret_cast<unsigned long long*>(base + kNoAllocWordsBytes + table_bytes);
+    DeviceGuard g(c->device);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    // validate and pack into the scratch table; the verdict comes back
+    // through the context's pinned words
+    if ((e = fos::launch_fill_u64(words, ~0ull, 1, st)) != hipSuccess ||
+        (e = fos::launch_fill_u64(words + 1, 0ull, 1, st)) != hipSuccess)
+        return hip_fail(c, e, "reset");
+    fos::PackArgs pa{p->n_items, p->max_layers, p->n_layers, p->mu_s, p->mu_a, p->g, p->n_layer, p->thickness,
+                     p->n_upper, p->n_lower, p->k_lower, p->mu0, p->photons, table, words, words + 1};
+    if ((e = fos::launch_pack(pa, st)) != hipSuccess) return hip_fail(c, e, "pack kernel");
+    if ((e = hipMemcpyAsync(c->err_host, words, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&c->aux_host[3], words + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess)
+        return hip_fail(c, e, "verdict copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "validation");
+    const unsigned long long w = *c->err_host;
+    if (w != ~0ull) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "item %llu layer %llu: invalid %s", w >> 16, (w >> 8) & 0xFF,
+                      field_name((int)(w & 0xFF)));
+        return fail(c, FOS_E_INVALID_ARG, buf);
+    }
+    fos_mc_launch L = merge(c->defaults, launch);
+    if (!(launch && launch->chunk) && !c->chunk_set)
+        L.chunk = auto_chunk_for(c->n_cu, p->n_items, (uint64_t)c->aux_host[3], L);
+    fos_status s = check_launch(c, L);
+    if (s != FOS_OK) return s;
+    // queue and walk, as fos_mc_execute does, on the scratch buffers
+    unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
+    if ((e = fos::launch_reset(tal, words + 2, p->n_items, fos::kNTally, st)) != hipSuccess ||
+        (e = fos::launch_chunk_scan(table, rf, p->n_items, L.chunk, 0, prefix, st)) != hipSuccess)
+        return hip_fail(c, e, "reset kernels");
+    fos::WalkArgs a{};
+    a.table = table;
+    a.n_items = p->n_items;
+    a.max_layers = p->max_layers;
+    a.rec_f4 = rf;
+    a.chunk_prefix = prefix;
+    a.chunk_counter = words + 2;
+    a.tallies = tal;
+    a.seed = seed;
+    a.seed_ptr = nullptr;
+    a.photon_cap = 0;
+    a.max_steps = (uint32_t)L.max_steps;
+    a.chunk = L.chunk;
+    a.refill_min = L.refill_min;
+    a.tail_lanes = L.tail_lanes < 0 ? 0 : L.tail_lanes;
+    if ((e = fos::launch_walk(a, c->n_cu * L.blocks_per_cu, L.block_size, st)) != hipSuccess)
+        return hip_fail(c, e, "walk kernel");
+    return FOS_OK;
 }
 
 static const char* optics_field_name(int code)

@@ -96,6 +96,9 @@ def lib():
         L.fos_mc_run.argtypes = [c_void_p, POINTER(fos_mc_problem), c_uint64, POINTER(fos_mc_launch),
                                  c_void_p, c_void_p]
         L.fos_mc_run.restype = c_int
+        L.fos_mc_run_noalloc.argtypes = [c_void_p, POINTER(fos_mc_problem), c_uint64, POINTER(fos_mc_launch),
+                                         c_void_p, c_void_p]
+        L.fos_mc_run_noalloc.restype = c_int
         L.fos_mc_prepared_items.argtypes = [c_void_p]
         L.fos_mc_prepared_items.restype = c_int32
         L.fos_mc_get_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
@@ -281,6 +284,12 @@ def fos_mc_run(ctx, problem: MCProblem, seed: int, tallies, launch=None, stream=
     _ptr(tallies, None, problem.n_items * N_TALLY)
     _check(ctx, lib().fos_mc_run(ctx, ctypes.byref(problem.struct), c_uint64(seed), _launch(launch),
                                  _ptr(tallies), _stream(stream)))
+
+
+def fos_mc_run_noalloc(ctx, problem: MCProblem, seed: int, tallies, launch=None, stream=None) -> None:
+    _ptr(tallies, None, problem.n_items * N_TALLY)
+    _check(ctx, lib().fos_mc_run_noalloc(ctx, ctypes.byref(problem.struct), c_uint64(seed), _launch(launch),
+                                         _ptr(tallies), _stream(stream)))
 
 
 def fos_mc_autotune(ctx, seed: int = 1, photon_cap: int = 0, stream=None):

@@ -80,12 +80,28 @@ struct GemmArgs {
     // second kernel adds the partials in split order into Cf
     int splits = 1;
     float* ws = nullptr;
+    bool partials = false;     // write the partial tiles (and column sums) to ws even for one K range
     // optional (TA, !TB only): the column sums of B over K for the first ncol
     // columns (a bias gradient when B is dZ), written to
     // csum[net * strideCsum + c]; they take the same K ranges and the same
     // ordered reduction as the product
     bool colsum = false; int ncol = 0;
     float* csum = nullptr; long strideCsum = 0;
+};
+
+// one ordered split-K sum of a batched training step (splitk_reduce_jobs)
+struct ReduceJob {
+    const float* ws;           // partial tiles [nets][splits][M][N], then column sums [nets][splits][N]
+    int splits, M, N;
+    float* C; long ldc; long strideC;
+    int rows_out, cols_out;    // the part of the M x N product written to C
+    int ncol;                  // column sums written (0 = none)
+    float* csum; long strideCsum;
+};
+constexpr int kMaxReduceJobs = 5;
+struct ReduceJobs {
+    ReduceJob job[kMaxReduceJobs];
+    int n;
 };
 
 struct StdArgs {
@@ -154,6 +170,16 @@ hipError_t launch_spectral_reduce(int designs, int lambdas, const float* rat, co
 hipError_t launch_pack_infer(const float* params, __bf16* pk, int nets, hipStream_t st);
 hipError_t launch_mlp_infer(const InferArgs& a, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st);
+// training step, grouped: a layer's split-K weight gradient (g1, partials
+// only) with the next dZ product (g2), the partials of a weight gradient
+// alone, and the ordered sums of several layers' partials in one launch
+hipError_t launch_backward_layer(const GemmArgs& g1, const GemmArgs& g2, int nets, hipStream_t st);
+hipError_t launch_gemm_partials(const GemmArgs& g, int nets, hipStream_t st);
+hipError_t launch_splitk_reduce_jobs(const ReduceJobs& jobs, int nets, hipStream_t st);
+hipError_t launch_input_layer(const StdArgs& a, const float* params, size_t pstride, float* Z1, __bf16* H1, int nets,
+                              hipStream_t st);
+hipError_t launch_adam_loss(const AdamArgs& a, const float* loss_rows, int rows, float* dst, float scale, int nets,
+                            hipStream_t st);
 // split-K ranges for a weight-gradient product over K rows: the largest power
 // of two up to kMaxSplits that keeps at least 8 k-steps of 32 per range
 constexpr int kMaxSplits = 16;
@@ -162,13 +188,7 @@ hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* m
                            const float* g, const float* n_layer, const float* thickness, const float* n_upper,
                            const float* n_lower, const float* k_lower, const float* mu0, float* x,
                            uint8_t* eligible, hipStream_t st);
-hipError_t launch_standardize(const StdArgs& a, int nets, hipStream_t st);
-hipError_t launch_first_layer(int rows_pad, const float* xs, const float* params, size_t pstride, float* Z1,
-                              __bf16* H1, int nets, hipStream_t st);
 hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st);
-hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
-                             size_t dstride, int nets, hipStream_t st);
-hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st);
 hipError_t launch_refresh_bf16(const float* w, __bf16* wb, int nets, hipStream_t st);
 hipError_t launch_feature_stats(const float* x, int64_t n, float* stats, hipStream_t st);
 // dst[m] = (add ? dst[m] : 0) + scale * (sum of member m's per-row losses [nets][rows])

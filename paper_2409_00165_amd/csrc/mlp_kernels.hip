@@ -10,22 +10,26 @@
 //                     fp32 accumulation, 64x64x32 LDS tiles, fused epilogues
 //                     (store fp32 / bias + GELU -> fp32 Z and bf16 H /
 //                     multiply by GELU'(Z) -> fp32 and bf16 dZ); grid.z walks
-//                     the ensemble members, and for the weight gradients
-//                     (K = the batch) their split-K ranges, whose partial
-//                     tiles splitk_reduce adds in a fixed order.
+//                     the ensemble members.
+//   backward_layer  : one layer of the backward pass in one launch: the
+//                     weight gradient H^T dZ cut into K ranges (the batch)
+//                     whose partial tiles, with the bias gradient as column
+//                     sums, go to a workspace, and the next dZ product.
+//   splitk_reduce_jobs : the partials of all five layers added in a fixed
+//                     order into the flat gradient, one launch.
 //   features        : transport problem -> the 8 raw features.
-//   standardize     : raw features -> standardised fp32 rows (+ bf16 padded
-//                     copy for the first layer's weight gradient), optional
-//                     per-member gather of a training batch.
-//   first_layer     : the 8-wide input layer on the VALU (fp32).
+//   input_layer     : gather and standardisation of a training batch and the
+//                     8-wide input layer on the VALU (fp32), one launch.
 //   softmax_ce      : softmax of the 3 logits, cross-entropy against the Monte
 //                     Carlo fractions, d loss / d logits = (p - y) / B.
-//   loss_sum        : the per-member loss of a batch (deterministic tree).
-//   adam            : Adam on fp32 master weights, refreshing bf16 copies.
+//   adam_loss       : Adam on fp32 master weights, refreshing bf16 copies, and
+//                     the per-member loss of the batch (deterministic tree).
 // Prediction (network + ensemble gate) is one fused kernel in mlp_infer.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "fos_mlp.hpp"
 
@@ -58,16 +62,18 @@ __device__ __forceinline__ float gelu_grad_f(float z)
 // ---------------------------------------------------------------------------
 constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 
+// One 64 x 64 output tile (bx, by) of member / K range bz (of nz = members x
+// splits) of the product g.
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, const int bx, const int by, const int bz, const int nz)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[kBM][kBK + kPad];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[kBN][kBK + kPad];
-    const int net = blockIdx.z / g.splits, split = blockIdx.z - net * g.splits;
+    const int net = bz / g.splits, split = bz - net * g.splits;
     const int kspan = g.K / g.splits;
     const __bf16* A = g.A + (size_t)net * g.strideA;
     const __bf16* B = g.B + (size_t)net * g.strideB;
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int m0 = by * kBM, n0 = bx * kBN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     floatx4 acc[2][2];
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     // column sums of B over the same K range (the bias gradient), by the first
     // M tile from the B tile in LDS: lane = column, wave w the rows 8w .. 8w + 7
     // of each k-step
-    const bool col_sums = g.colsum && blockIdx.y == 0 && n0 + lane < g.ncol;
+    const bool col_sums = g.colsum && by == 0 && n0 + lane < g.ncol;
     float csv = 0.f;
     // the next k-step's tiles are loaded into registers while this one
     // multiplies (one register set, written to LDS after the barrier)
@@ -132,21 +138,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         __syncthreads();
     }
 
-    if (g.colsum && blockIdx.y == 0) {   // the 4 waves' column sums
+    if (g.colsum && by == 0) {   // the 4 waves' column sums
         __shared__ float csl[4][64];
         const int c = n0 + lane;
         csl[wave][lane] = csv;
         __syncthreads();
         if (wave == 0 && c < g.ncol) {
             const float v = (csl[0][lane] + csl[1][lane]) + (csl[2][lane] + csl[3][lane]);
-            if (g.splits == 1) g.csum[(size_t)net * g.strideCsum + c] = v;
-            else g.ws[(size_t)gridDim.z * g.M * g.N + (size_t)blockIdx.z * g.N + c] = v;
+            if (g.splits == 1 && !g.partials) g.csum[(size_t)net * g.strideCsum + c] = v;
+            else g.ws[(size_t)nz * g.M * g.N + (size_t)bz * g.N + c] = v;
         }
     }
     float* Cf = g.Cf ? g.Cf + (size_t)net * g.strideC : nullptr;
     long ldc = g.ldc;
-    if (EPI == kEpiStore && g.splits > 1) {   // partial tile of this K range
-        Cf = g.ws + (size_t)blockIdx.z * g.M * g.N;
+    if (EPI == kEpiStore && (g.splits > 1 || g.partials)) {   // partial tile of this K range
+        Cf = g.ws + (size_t)bz * g.M * g.N;
         ldc = g.N;
     }
     __bf16* Cb = g.Cb ? g.Cb + (size_t)net * g.strideCb : nullptr;
@@ -176,38 +182,94 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             }
 }
 
-// C[net] (ldc, strideC) = sum over s = 0 .. splits-1, in that order, of the
-// partial tiles ws[net][s] (M x N, dense); likewise the column sums, whose
-// partials follow the tiles of all nets
-__global__ void splitk_reduce_kernel(const float* __restrict__ ws, int splits, int M, int N, float* C, long ldc,
-                                     long strideC, int ncol, float* csum, long strideCsum)
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 {
+    gemm_tile<TA, TB, EPI>(g, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// A layer of the backward pass in one launch: the split-K weight gradient
+// dW = H^T dZ (g1, partial tiles to its workspace) and, independent of it,
+// the next dZ = (dZ W^T) * gelu'(Z) (g2).  The first blocks take g1's tiles.
+__global__ __launch_bounds__(256) void backward_layer_kernel(GemmArgs g1, GemmArgs g2, int nets)
+{
+    const int gx1 = g1.N / kBN, gy1 = g1.M / kBM, gz1 = nets * g1.splits;
+    int b = blockIdx.x;
+    if (b < gx1 * gy1 * gz1) {
+        gemm_tile<true, false, kEpiStore>(g1, b % gx1, (b / gx1) % gy1, b / (gx1 * gy1), gz1);
+    } else {
+        b -= gx1 * gy1 * gz1;
+        const int gx2 = g2.N / kBN, gy2 = g2.M / kBM;
+        gemm_tile<false, true, kEpiGeluGrad>(g2, b % gx2, (b / gx2) % gy2, b / (gx2 * gy2), nets);
+    }
+}
+
+// The ordered split-K sums of several weight gradients in one launch
+// (grid.z = job): C[net][row][col] (ldc, strideC, rows < rows_out and cols <
+// cols_out, so padded products land in the flat gradient directly) = the sum
+// over s = 0 .. splits-1, in that order, of the partial tiles ws[net][s], and
+// likewise the column sums.
+__global__ void splitk_reduce_jobs_kernel(ReduceJobs jobs, int nets)
+{
+    const ReduceJob& J = jobs.job[blockIdx.z];
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int net = blockIdx.y;
-    const size_t MN = (size_t)M * N;
+    const size_t MN = (size_t)J.M * J.N;
     if (e >= MN) return;
-    const float* p = ws + (size_t)net * splits * MN + e;
-    float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += p[(size_t)k * MN];
-    C[(size_t)net * strideC + (e / N) * ldc + e % N] = s;
-    if (csum && e < (size_t)ncol) {
-        const float* q = ws + (size_t)gridDim.y * splits * MN + (size_t)net * splits * N + e;
+    const float* p = J.ws + (size_t)net * J.splits * MN + e;
+    const int row = (int)(e / J.N), col = (int)(e % J.N);
+    if (row < J.rows_out && col < J.cols_out) {
+        float s = 0.0f;
+        for (int k = 0; k < J.splits; ++k) s += p[(size_t)k * MN];
+        J.C[(size_t)net * J.strideC + (size_t)row * J.ldc + col] = s;
+    }
+    if (J.csum && e < (size_t)J.ncol) {
+        const float* q = J.ws + (size_t)nets * J.splits * MN + (size_t)net * J.splits * J.N + e;
         float t = 0.0f;
-        for (int k = 0; k < splits; ++k) t += q[(size_t)k * N];
-        csum[(size_t)net * strideCsum + e] = t;
+        for (int k = 0; k < J.splits; ++k) t += q[(size_t)k * J.N];
+        J.csum[(size_t)net * J.strideCsum + e] = t;
     }
 }
 
 template <bool TA, bool TB, int EPI>
 static hipError_t launch_gemm_t(const GemmArgs& g, int nets, hipStream_t st)
 {
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), dim3(g.N / kBN, g.M / kBM, nets * g.splits), dim3(256), 0, st, g);
-    if (g.splits > 1) {
-        const size_t MN = (size_t)g.M * g.N;
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256), nets), dim3(256), 0, st, g.ws,
-                           g.splits, g.M, g.N, g.Cf, g.ldc, g.strideC, g.ncol, g.colsum ? g.csum : nullptr,
-                           g.strideCsum);
-    }
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), dim3(g.N / kBN, g.M / kBM, nets), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+static bool gemm_shape_ok(const GemmArgs& g)
+{
+    return g.M > 0 && g.N > 0 && g.K > 0 && g.M % kBM == 0 && g.N % kBN == 0 && g.K % kBK == 0 &&
+           g.splits >= 1 && g.splits <= kMaxSplits && g.K % (g.splits * kBK) == 0;
+}
+
+hipError_t launch_backward_layer(const GemmArgs& g1, const GemmArgs& g2, int nets, hipStream_t st)
+{
+    if (!gemm_shape_ok(g1) || !gemm_shape_ok(g2) || g2.splits != 1 || !g1.ws || !g2.Cb || !g2.Z ||
+        (g1.colsum && (!g1.csum || g1.ncol < 1 || g1.ncol > g1.N)))
+        return hipErrorInvalidValue;
+    const int blocks = (g1.N / kBN) * (g1.M / kBM) * nets * g1.splits + (g2.N / kBN) * (g2.M / kBM) * nets;
+    hipLaunchKernelGGL(backward_layer_kernel, dim3(blocks), dim3(256), 0, st, g1, g2, nets);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_partials(const GemmArgs& g, int nets, hipStream_t st)
+{
+    if (!gemm_shape_ok(g) || !g.ws || (g.colsum && (!g.csum || g.ncol < 1 || g.ncol > g.N)))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_kernel<true, false, kEpiStore>), dim3(g.N / kBN, g.M / kBM, nets * g.splits), dim3(256),
+                       0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_splitk_reduce_jobs(const ReduceJobs& jobs, int nets, hipStream_t st)
+{
+    if (jobs.n < 1 || jobs.n > kMaxReduceJobs) return hipErrorInvalidValue;
+    size_t mn = 0;
+    for (int j = 0; j < jobs.n; ++j) mn = std::max(mn, (size_t)jobs.job[j].M * jobs.job[j].N);
+    hipLaunchKernelGGL(splitk_reduce_jobs_kernel, dim3((unsigned)((mn + 255) / 256), nets, jobs.n), dim3(256), 0, st,
+                       jobs, nets);
     return hipGetLastError();
 }
 
@@ -220,17 +282,10 @@ int gemm_splits(int K)
 
 hipError_t launch_gemm(const GemmArgs& g, bool ta, bool tb, int epi, int nets, hipStream_t st)
 {
-    if (g.M % kBM || g.N % kBN || g.K % kBK || g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
-    if (g.splits < 1 || g.splits > kMaxSplits || g.K % (g.splits * kBK) ||
-        (g.splits > 1 && (epi != kEpiStore || !g.ws || !g.Cf)))
-        return hipErrorInvalidValue;
-    if (g.colsum && (!ta || tb || !g.csum || g.ncol < 1 || g.ncol > g.N))
-        return hipErrorInvalidValue;
+    if (!gemm_shape_ok(g) || g.splits != 1 || g.partials || g.colsum) return hipErrorInvalidValue;
     if (!ta && !tb && epi == kEpiBiasGelu) return launch_gemm_t<false, false, kEpiBiasGelu>(g, nets, st);
     if (!ta && !tb && epi == kEpiStore) return launch_gemm_t<false, false, kEpiStore>(g, nets, st);
     if (!ta && tb && epi == kEpiGeluGrad) return launch_gemm_t<false, true, kEpiGeluGrad>(g, nets, st);
-    if (!ta && tb && epi == kEpiStore) return launch_gemm_t<false, true, kEpiStore>(g, nets, st);
-    if (ta && !tb && epi == kEpiStore) return launch_gemm_t<true, false, kEpiStore>(g, nets, st);
     return hipErrorInvalidValue;
 }
 
@@ -264,46 +319,60 @@ __global__ void features_kernel(int n, int L, const int32_t* n_layers, const flo
     if (eligible) eligible[i] = (n_layers[i] == 1 && n_upper[i] == 1.0f) ? 1 : 0;
 }
 
-// row r of member m takes source row idx = perm(m, r) (or r), standardised
-__global__ void standardize_kernel(StdArgs a)
+// The standardisation of a training batch and the first layer in one
+// launch: block (b, m) takes rows 16b .. 16b + 15 of member m; its first 16
+// threads gather and standardise one row each (writing xs, the
+// bf16 copy xb padded to 64 for the first layer's weight gradient, and ys),
+// then thread t computes Z1 = X W1 + b1 (fp32, K = 8) and H1 = bf16(gelu(Z1))
+// for neuron t of the 16 rows.
+constexpr int kInRows = 16;
+__global__ __launch_bounds__(256) void input_layer_kernel(StdArgs a, const float* params, size_t pstride, float* Z1,
+                                                          __bf16* H1)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y;
-    if (r >= a.rows) return;
-    int64_t src = a.base + r;
-    if (a.perm_mul) src = (int64_t)(((uint64_t)a.perm_mul[m] * (uint64_t)(a.base + r) + a.perm_add[m]) % (uint64_t)a.n_src);
-    const bool valid = src < a.n_src;
-    float* xs = a.xs + ((size_t)m * a.rows_pad + r) * kFeatures;
-    __bf16* xb = a.xb ? a.xb + ((size_t)m * a.rows_pad + r) * kPadIn : nullptr;
-    for (int k = 0; k < kFeatures; ++k) {
-        const float v = valid ? (a.x[(size_t)src * kFeatures + k] - a.mean[k]) * a.inv_std[k] : 0.0f;
-        xs[k] = v;
-        if (xb) xb[k] = (__bf16)v;
+    __shared__ float sx[kInRows][kFeatures];
+    const int m = blockIdx.y, t = threadIdx.x;
+    const int r0 = blockIdx.x * kInRows;
+    if (t < kInRows) {
+        const int r = r0 + t;
+        float* xs = a.xs + ((size_t)m * a.rows_pad + r) * kFeatures;
+        if (r < a.rows) {
+            int64_t src = a.base + r;
+            if (a.perm_mul)
+                src = (int64_t)(((uint64_t)a.perm_mul[m] * (uint64_t)(a.base + r) + a.perm_add[m]) % (uint64_t)a.n_src);
+            const bool valid = src < a.n_src;
+            __bf16* xb = a.xb ? a.xb + ((size_t)m * a.rows_pad + r) * kPadIn : nullptr;
+            for (int k = 0; k < kFeatures; ++k) {
+                const float v = valid ? (a.x[(size_t)src * kFeatures + k] - a.mean[k]) * a.inv_std[k] : 0.0f;
+                xs[k] = v;
+                sx[t][k] = v;
+                if (xb) xb[k] = (__bf16)v;
+            }
+            if (xb)
+                for (int k = kFeatures; k < kPadIn; ++k) xb[k] = (__bf16)0.0f;
+            if (a.y && a.ys) {
+                float* ys = a.ys + ((size_t)m * a.rows_pad + r) * 3;
+                for (int c = 0; c < 3; ++c) ys[c] = valid ? a.y[(size_t)src * 3 + c] : 0.0f;
+            }
+        } else {
+            for (int k = 0; k < kFeatures; ++k) sx[t][k] = r < a.rows_pad ? xs[k] : 0.0f;
+        }
     }
-    if (xb)
-        for (int k = kFeatures; k < kPadIn; ++k) xb[k] = (__bf16)0.0f;
-    if (a.y && a.ys) {
-        float* ys = a.ys + ((size_t)m * a.rows_pad + r) * 3;
-        for (int c = 0; c < 3; ++c) ys[c] = valid ? a.y[(size_t)src * 3 + c] : 0.0f;
-    }
-}
-
-// Z1 = X W1 + b1 (fp32, K = 8), H1 = bf16(gelu(Z1)); one thread per output
-__global__ void first_layer_kernel(int rows_pad, const float* xs, const float* params, size_t pstride,
-                                   float* Z1, __bf16* H1)
-{
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y;
-    if (idx >= (size_t)rows_pad * kHidden) return;
-    const int r = (int)(idx / kHidden), n = (int)(idx % kHidden);
+    __syncthreads();
     const float* P = params + (size_t)m * pstride;
-    const float* x = xs + ((size_t)m * rows_pad + r) * kFeatures;
-    float z = P[kOffB1 + n];
+    float w[kFeatures];
 #pragma unroll
-    for (int k = 0; k < kFeatures; ++k) z = fmaf(x[k], P[kOffW1 + k * kHidden + n], z);
-    const size_t o = (size_t)m * rows_pad * kHidden + idx;
-    if (Z1) Z1[o] = z;
-    H1[o] = (__bf16)gelu_f(z);
+    for (int k = 0; k < kFeatures; ++k) w[k] = P[kOffW1 + k * kHidden + t];
+    const float b = P[kOffB1 + t];
+    for (int i = 0; i < kInRows; ++i) {
+        const int r = r0 + i;
+        if (r >= a.rows_pad) break;
+        float z = b;
+#pragma unroll
+        for (int k = 0; k < kFeatures; ++k) z = fmaf(sx[i][k], w[k], z);
+        const size_t o = ((size_t)m * a.rows_pad + r) * kHidden + t;
+        if (Z1) Z1[o] = z;
+        H1[o] = (__bf16)gelu_f(z);
+    }
 }
 
 // softmax over the 3 logits (columns 0..2 of a 64-wide fp32 row) + b5;
@@ -339,23 +408,27 @@ __global__ void softmax_ce_kernel(SoftmaxArgs a)
     }
 }
 
-// copy a [rows][cols] sub-block of a padded fp32 matrix into the flat gradient
-__global__ void copy_block_kernel(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
-                                  size_t dstride)
+// The Adam step of a training step and, in the extra last block of each
+// member, its batch loss (loss_sum_kernel's fixed tree) in one launch.
+__global__ __launch_bounds__(256) void adam_loss_kernel(AdamArgs a, const float* __restrict__ loss_rows, int rows,
+                                                        float* dst, float scale)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y;
-    if (idx >= rows * cols) return;
-    const int r = idx / cols, c = idx % cols;
-    dst[(size_t)m * dstride + idx] = src[(size_t)m * sstride + (size_t)r * src_ld + c];
-}
-
-// Adam on the flat fp32 parameters of every member, then the bf16 copies:
-// W2..W4 [256][256] and the two padded copies of W5.
-__global__ void adam_kernel(AdamArgs a)
-{
-    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int m = blockIdx.y;
+    const int m = blockIdx.y, t = threadIdx.x;
+    if (dst && blockIdx.x == gridDim.x - 1) {
+        __shared__ float part[256];
+        const float* l = loss_rows + (size_t)m * rows;
+        float s = 0.f;
+        for (int r = t; r < rows; r += 256) s += l[r];
+        part[t] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) part[t] += part[t + o];
+            __syncthreads();
+        }
+        if (t == 0) dst[m] += scale * part[0];
+        return;
+    }
+    const size_t j = (size_t)blockIdx.x * blockDim.x + t;
     if (j >= (size_t)kParams) return;
     const size_t o = (size_t)m * kParams + j;
     const float g = a.grads[o];
@@ -632,38 +705,25 @@ hipError_t launch_features(int n, int L, const int32_t* n_layers, const float* m
     return hipGetLastError();
 }
 
-hipError_t launch_standardize(const StdArgs& a, int nets, hipStream_t st)
-{
-    hipLaunchKernelGGL(standardize_kernel, dim3((a.rows_pad + 255) / 256, nets), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_first_layer(int rows_pad, const float* xs, const float* params, size_t pstride, float* Z1,
-                              __bf16* H1, int nets, hipStream_t st)
-{
-    const size_t tot = (size_t)rows_pad * kHidden;
-    hipLaunchKernelGGL(first_layer_kernel, dim3((unsigned)((tot + 255) / 256), nets), dim3(256), 0, st, rows_pad,
-                       xs, params, pstride, Z1, H1);
-    return hipGetLastError();
-}
-
 hipError_t launch_softmax_ce(const SoftmaxArgs& a, int nets, hipStream_t st)
 {
     hipLaunchKernelGGL(softmax_ce_kernel, dim3((a.rows_pad + 255) / 256, nets), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_block(const float* src, int src_ld, size_t sstride, int rows, int cols, float* dst,
-                             size_t dstride, int nets, hipStream_t st)
+hipError_t launch_input_layer(const StdArgs& a, const float* params, size_t pstride, float* Z1, __bf16* H1, int nets,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(copy_block_kernel, dim3((rows * cols + 255) / 256, nets), dim3(256), 0, st, src, src_ld,
-                       sstride, rows, cols, dst, dstride);
+    hipLaunchKernelGGL(input_layer_kernel, dim3((a.rows_pad + kInRows - 1) / kInRows, nets), dim3(kHidden), 0, st, a,
+                       params, pstride, Z1, H1);
     return hipGetLastError();
 }
 
-hipError_t launch_adam(const AdamArgs& a, int nets, hipStream_t st)
+hipError_t launch_adam_loss(const AdamArgs& a, const float* loss_rows, int rows, float* dst, float scale, int nets,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256, nets), dim3(256), 0, st, a);
+    const unsigned blocks = (unsigned)((kParams + 255) / 256) + (dst ? 1u : 0u);
+    hipLaunchKernelGGL(adam_loss_kernel, dim3(blocks, nets), dim3(256), 0, st, a, loss_rows, rows, dst, scale);
     return hipGetLastError();
 }
 

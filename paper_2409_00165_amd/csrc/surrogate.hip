@@ -20,6 +20,12 @@ using fosrt::hip_fail;
 namespace {
 
 
+// split-K partials of the five weight gradients of a training step, one
+// region per layer: [nets][splits][M][N] tiles, then [nets][splits][N] column
+// sums, M x N at most 256 x 256
+constexpr int kSplitkLayers = 5;
+constexpr size_t kSplitkLayerFloats = (size_t)fos::kNets * fos::kMaxSplits * (fos::kHidden + 1) * fos::kHidden;
+
 hipError_t alloc_ws(fos_sur_state& S, void** p, size_t bytes)
 {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
@@ -84,7 +90,7 @@ hipError_t ensure_ws(fos_sur_state& S, int rows)
     }
     A(&S.dW5pad, (size_t)fos::kNets * fos::kHidden * fos::kPadOut * sizeof(float));
     A(&S.dW1pad, (size_t)fos::kNets * fos::kPadIn * fos::kHidden * sizeof(float));
-    A(&S.splitk, (size_t)fos::kNets * fos::kMaxSplits * (fos::kHidden + 1) * fos::kHidden * sizeof(float));
+    A(&S.splitk, kSplitkLayers * kSplitkLayerFloats * sizeof(float));
     if (e == hipSuccess) S.ws_rows = rows;
     return e;
 }
@@ -104,15 +110,17 @@ fos::GemmArgs gemm(int M, int N, int K, const __bf16* A, long lda, long sA, cons
     return g;
 }
 
-// Training forward through the 4 hidden layers and the logits for `rows_pad`
-// rows per member whose standardised features are in S.xs; the
-// pre-activations Z1..Z4 and activations H1..H4 are kept for the backward
-// pass.  (Prediction uses the fused kernel of mlp_infer.hip instead.)
-hipError_t forward(fos_sur_state& S, int rows_pad, hipStream_t st)
+// Training forward: the batch rows of `sa` gathered and standardised into
+// S.xs, then the 4 hidden layers and the logits for sa.rows_pad rows per
+// member; the pre-activations Z1..Z4 and activations H1..H4 are kept for the
+// backward pass.  (Prediction uses the fused kernel of mlp_infer.hip instead.)
+hipError_t forward(fos_sur_state& S, const fos::StdArgs& sa, hipStream_t st)
 {
+    const int rows_pad = sa.rows_pad;
     const long RH = (long)rows_pad * fos::kHidden;
     const long PS = (long)fos::kParams, BS = (long)fos::kBfParams;
-    hipError_t e = fos::launch_first_layer(rows_pad, S.xs, S.params, fos::kParams, S.Z[0], S.H[0], fos::kNets, st);
+    // gather + standardisation and the first layer in one launch
+    hipError_t e = fos::launch_input_layer(sa, S.params, fos::kParams, S.Z[0], S.H[0], fos::kNets, st);
     if (e != hipSuccess) return e;
     const size_t wof[3] = {fos::kBfW2, fos::kBfW3, fos::kBfW4};
     const size_t bof[3] = {fos::kOffB2, fos::kOffB3, fos::kOffB4};
@@ -129,33 +137,39 @@ hipError_t forward(fos_sur_state& S, int rows_pad, hipStream_t st)
 }
 
 // Backward pass after a training forward + softmax_ce: fills S.grads.  The
-// weight gradients reduce over the batch rows, so they run split-K.
+// weight gradients reduce over the batch rows, so they run split-K; each
+// layer's weight-gradient partials and the next layer's dZ product share one
+// launch, and one more launch adds the partials of all five layers in split
+// order into the flat gradient (biases: the column sums of dZ, folded into
+// the same products).
 hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
 {
     const int R = rows;                       // rows_pad == rows in training
     const long RH = (long)R * fos::kHidden;
     const long PS = (long)fos::kParams, BS = (long)fos::kBfParams;
     const int splits = fos::gemm_splits(R);
-    // split-K weight gradient, with the bias gradient (the column sums of the
-    // same bf16 dZ operand) folded into the product
-    auto split_k = [&](fos::GemmArgs& a, int ncol, float* bias_grad) {
-        a.splits = splits; a.ws = S.splitk;
+    fos::ReduceJobs jobs{};
+    // weight-gradient partials of layer slot l into its workspace region, with
+    // the bias gradient from the column sums of the same dZ operand
+    auto partials = [&](fos::GemmArgs& a, int l, int ncol, float* C, long ldc, int rows_out, int cols_out,
+                        float* bias_grad) {
+        a.splits = splits; a.ws = S.splitk + (size_t)l * kSplitkLayerFloats; a.partials = true;
         a.colsum = true; a.ncol = ncol; a.csum = bias_grad; a.strideCsum = PS;
+        fos::ReduceJob& J = jobs.job[jobs.n++];
+        J.ws = a.ws; J.splits = splits; J.M = a.M; J.N = a.N;
+        J.C = C; J.ldc = ldc; J.strideC = PS; J.rows_out = rows_out; J.cols_out = cols_out;
+        J.ncol = ncol; J.csum = bias_grad; J.strideCsum = PS;
     };
     hipError_t e;
-    // dW5 = H4^T dlog (padded), db5 = colsum(dlog)
-    fos::GemmArgs g = gemm(fos::kHidden, fos::kPadOut, R, S.H[3], fos::kHidden, RH, S.dlog, fos::kPadOut,
-                           (long)R * fos::kPadOut, S.dW5pad, fos::kPadOut, (long)fos::kHidden * fos::kPadOut,
-                           nullptr, 0, nullptr, 0, nullptr, 0);
-    split_k(g, 3, S.grads + fos::kOffB5);
-    if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
-    if ((e = fos::launch_copy_block(S.dW5pad, fos::kPadOut, (size_t)fos::kHidden * fos::kPadOut, fos::kHidden, 3,
-                                    S.grads + fos::kOffW5, fos::kParams, fos::kNets, st)) != hipSuccess)
-        return e;
+    // dW5 = H4^T dlog (padded to 64 columns, the first 3 kept), db5 = colsum(dlog);
     // dZ4 = (dlog W5^T) * gelu'(Z4)
-    g = gemm(R, fos::kHidden, fos::kPadK5, S.dlog, fos::kPadOut, (long)R * fos::kPadOut, S.wb + fos::kBfW5t,
-             fos::kPadK5, BS, nullptr, fos::kHidden, RH, S.dZ[0], RH, nullptr, 0, S.Z[3], RH);
-    if ((e = fos::launch_gemm(g, false, true, fos::kEpiGeluGrad, fos::kNets, st)) != hipSuccess) return e;
+    fos::GemmArgs g1 = gemm(fos::kHidden, fos::kPadOut, R, S.H[3], fos::kHidden, RH, S.dlog, fos::kPadOut,
+                            (long)R * fos::kPadOut, nullptr, fos::kPadOut, 0, nullptr, 0, nullptr, 0, nullptr, 0);
+    partials(g1, 0, 3, S.grads + fos::kOffW5, 3, fos::kHidden, 3, S.grads + fos::kOffB5);
+    fos::GemmArgs g2 = gemm(R, fos::kHidden, fos::kPadK5, S.dlog, fos::kPadOut, (long)R * fos::kPadOut,
+                            S.wb + fos::kBfW5t, fos::kPadK5, BS, nullptr, fos::kHidden, RH, S.dZ[0], RH, nullptr, 0,
+                            S.Z[3], RH);
+    if ((e = fos::launch_backward_layer(g1, g2, fos::kNets, st)) != hipSuccess) return e;
     // layers 4, 3, 2: dW = H_{l-1}^T dZ_l, db = colsum(dZ_l), dZ_{l-1} = (dZ_l W^T) * gelu'(Z_{l-1})
     const size_t wof[3] = {fos::kOffW4, fos::kOffW3, fos::kOffW2};
     const size_t bof[3] = {fos::kOffB4, fos::kOffB3, fos::kOffB2};
@@ -163,22 +177,22 @@ hipError_t backward(fos_sur_state& S, int rows, hipStream_t st)
     int cur = 0;
     for (int s = 0; s < 3; ++s) {
         const int hl = 2 - s;                 // H index of the layer input: H3, H2, H1
-        g = gemm(fos::kHidden, fos::kHidden, R, S.H[hl], fos::kHidden, RH, S.dZ[cur], fos::kHidden, RH,
-                 S.grads + wof[s], fos::kHidden, PS, nullptr, 0, nullptr, 0, nullptr, 0);
-        split_k(g, fos::kHidden, S.grads + bof[s]);
-        if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
-        g = gemm(R, fos::kHidden, fos::kHidden, S.dZ[cur], fos::kHidden, RH, S.wb + wbf[s], fos::kHidden, BS,
-                 nullptr, fos::kHidden, RH, S.dZ[cur ^ 1], RH, nullptr, 0, S.Z[hl], RH);
-        if ((e = fos::launch_gemm(g, false, true, fos::kEpiGeluGrad, fos::kNets, st)) != hipSuccess) return e;
+        g1 = gemm(fos::kHidden, fos::kHidden, R, S.H[hl], fos::kHidden, RH, S.dZ[cur], fos::kHidden, RH, nullptr,
+                  fos::kHidden, 0, nullptr, 0, nullptr, 0, nullptr, 0);
+        partials(g1, 1 + s, fos::kHidden, S.grads + wof[s], fos::kHidden, fos::kHidden, fos::kHidden,
+                 S.grads + bof[s]);
+        g2 = gemm(R, fos::kHidden, fos::kHidden, S.dZ[cur], fos::kHidden, RH, S.wb + wbf[s], fos::kHidden, BS, nullptr,
+                  fos::kHidden, RH, S.dZ[cur ^ 1], RH, nullptr, 0, S.Z[hl], RH);
+        if ((e = fos::launch_backward_layer(g1, g2, fos::kNets, st)) != hipSuccess) return e;
         cur ^= 1;
     }
-    // layer 1: dW1 = X^T dZ1 (inputs padded to 64), db1 = colsum(dZ1)
-    g = gemm(fos::kPadIn, fos::kHidden, R, S.xb, fos::kPadIn, (long)R * fos::kPadIn, S.dZ[cur], fos::kHidden, RH,
-             S.dW1pad, fos::kHidden, (long)fos::kPadIn * fos::kHidden, nullptr, 0, nullptr, 0, nullptr, 0);
-    split_k(g, fos::kHidden, S.grads + fos::kOffB1);
-    if ((e = fos::launch_gemm(g, true, false, fos::kEpiStore, fos::kNets, st)) != hipSuccess) return e;
-    return fos::launch_copy_block(S.dW1pad, fos::kHidden, (size_t)fos::kPadIn * fos::kHidden, fos::kFeatures,
-                                  fos::kHidden, S.grads + fos::kOffW1, fos::kParams, fos::kNets, st);
+    // layer 1: dW1 = X^T dZ1 (inputs padded to 64, the first 8 rows kept), db1 = colsum(dZ1)
+    g1 = gemm(fos::kPadIn, fos::kHidden, R, S.xb, fos::kPadIn, (long)R * fos::kPadIn, S.dZ[cur], fos::kHidden, RH,
+              nullptr, fos::kHidden, 0, nullptr, 0, nullptr, 0, nullptr, 0);
+    partials(g1, 4, fos::kHidden, S.grads + fos::kOffW1, fos::kHidden, fos::kFeatures, fos::kHidden,
+             S.grads + fos::kOffB1);
+    if ((e = fos::launch_gemm_partials(g1, fos::kNets, st)) != hipSuccess) return e;
+    return fos::launch_splitk_reduce_jobs(jobs, fos::kNets, st);
 }
 
 hipError_t softmax(fos_sur_state& S, int rows, int rows_pad, bool targets, hipStream_t st)
@@ -325,8 +339,7 @@ fos_status fos_sur_train(fos_ctx* c, const float* x, const float* y, int64_t n, 
         const uint64_t* pm = S.perm + (size_t)ep * 2 * fos::kNets;
         for (int64_t s = 0; s < steps_per_epoch; ++s, ++step) {
             fos::StdArgs sa = std_args(S, x, y, n, s * B, B, B, pm);
-            if ((e = fos::launch_standardize(sa, fos::kNets, st)) != hipSuccess) return hip_fail(c, e, "gather");
-            if ((e = forward(S, B, st)) != hipSuccess) return hip_fail(c, e, "forward");
+            if ((e = forward(S, sa, st)) != hipSuccess) return hip_fail(c, e, "forward");
             if ((e = softmax(S, B, B, true, st)) != hipSuccess) return hip_fail(c, e, "softmax");
             if ((e = backward(S, B, st)) != hipSuccess) return hip_fail(c, e, "backward");
             const double frac = total > 1 ? (double)step / (double)(total - 1) : 1.0;
@@ -335,12 +348,12 @@ fos_status fos_sur_train(fos_ctx* c, const float* x, const float* y, int64_t n, 
             fos::AdamArgs aa{S.params, S.m, S.v, S.grads, S.wb, lr, 0.9f, 0.999f, 1e-8f,
                              (float)(1.0 / (1.0 - std::pow(0.9, (double)S.adam_step))),
                              (float)(1.0 / (1.0 - std::pow(0.999, (double)S.adam_step)))};
-            if ((e = fos::launch_adam(aa, fos::kNets, st)) != hipSuccess) return hip_fail(c, e, "adam");
-            if (o->loss_history &&
-                (e = fos::launch_loss_sum(S.loss_rows, B, o->loss_history + (size_t)ep * fos::kNets,
-                                          (float)(1.0 / ((double)B * steps_per_epoch)), true, fos::kNets, st)) !=
-                    hipSuccess)
-                return hip_fail(c, e, "loss history");
+            // the Adam step and the batch loss of the epoch's history in one launch
+            if ((e = fos::launch_adam_loss(aa, S.loss_rows, B,
+                                           o->loss_history ? o->loss_history + (size_t)ep * fos::kNets : nullptr,
+                                           (float)(1.0 / ((double)B * steps_per_epoch)), fos::kNets, st)) !=
+                hipSuccess)
+                return hip_fail(c, e, "adam");
         }
     }
     // host copy of the stats for save()
@@ -389,8 +402,7 @@ fos_status fos_sur_grad(fos_ctx* c, const float* x, const float* y, int64_t n, f
     if (e != hipSuccess) return hip_fail(c, e, "workspace");
     const int R = (int)n;
     fos::StdArgs sa = std_args(S, x, y, n, 0, R, R, nullptr);
-    if ((e = fos::launch_standardize(sa, fos::kNets, st)) != hipSuccess ||
-        (e = forward(S, R, st)) != hipSuccess || (e = softmax(S, R, R, true, st)) != hipSuccess ||
+    if ((e = forward(S, sa, st)) != hipSuccess || (e = softmax(S, R, R, true, st)) != hipSuccess ||
         (e = backward(S, R, st)) != hipSuccess)
         return hip_fail(c, e, "gradient");
     if ((e = hipMemcpyAsync(grads, S.grads, (size_t)fos::kNets * fos::kParams * sizeof(float),

@@ -40,6 +40,8 @@ STEP_SLOTS = 160.0
 # one full-rate VALU lane-op slot per FMA lane per cycle.
 VALU_PEAK = 157.3e12 / 2.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_two_species_500_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "walk_two_species_500_valu_counters.txt")
+FP32_PEAK = 157.3e12      # FP32 vector FLOP/s (packed), MI355X
 KERNEL_SOURCES = ["paper_2409_00165_amd/csrc/mc_kernels.hip", "paper_2409_00165_amd/csrc/fos_device.hpp"]
 
 
@@ -51,19 +53,24 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per walk launch from the committed counter summary, or None
-    when the kernel sources changed since the counters were taken."""
+def profile_value(path: str, key: str):
+    """A figure from a committed counter summary ("key: value" lines), or
+    None when the kernel sources changed since the counters were taken."""
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     if kv.get("kernel_hash", "").strip() != kernel_hash():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter summary."""
+    return profile_value(TRAFFIC_FILE, "traffic_bytes_per_launch")
 
 
 def _cpu_model() -> str:
@@ -116,6 +123,72 @@ def gpu_problem(ctx, wl, device="cuda"):
                          t(geo["n_lower"], np.float32), t(geo["k_lower"], np.float32), t(geo["mu0"], np.float32),
                          ph)
     return prob, (mus, mua, g)
+
+
+# Algorithmic work of one photon-step (a scattering step) by instruction
+# class: one Philox4x32-10 block; 47 full-rate FP32/integer operations (four
+# 24-bit uniforms 12, free path 6, geometry and move 11, albedo test 1,
+# Henyey-Greenstein sample 10, direction update 7); and one each of log,
+# reciprocal, square root and cosine.
+STEP_CLASSES = {"philox": 1, "full_rate": 47, "log": 1, "rcp": 1, "sqrt": 1, "cos": 1}
+FULL_RATE_FORMS = ("fma", "fmac", "mul")
+ISSUE_ITERS = {"fma": 300_000, "fmac": 300_000, "mul": 300_000, "rcp": 80_000, "sqrt": 80_000, "log": 80_000,
+               "cos": 80_000, "philox": 25_000}
+
+
+def issue_rates(h, stream, reps: int = 3):
+    """Measured throughput of each instruction form of the walk (lane
+    operations per second; Philox: blocks per second), best of `reps`
+    launches after a warm-up, HIP events on `stream`."""
+    import torch
+    from paper_2409_00165_amd import fos
+    sink = torch.zeros(fos.fos_issue_threads(h), dtype=torch.float32, device="cuda")
+    out = {}
+    for kind, iters in ISSUE_ITERS.items():
+        fos.fos_issue_run(h, kind, iters, sink, stream=stream)
+        best = None
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ops = fos.fos_issue_run(h, kind, iters, sink, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        out[kind] = {"ops_per_launch": ops, "ms": best, "rate": ops / (best / 1e3)}
+    return out
+
+
+def issue_ceiling_step_time(rates) -> float:
+    """Seconds per photon-step if the walk issued only its algorithmic work
+    at the measured rates, one class after another (no overlap); the
+    full-rate operations at the fastest measured full-rate form."""
+    full = max(rates[k]["rate"] for k in FULL_RATE_FORMS)
+    return sum(n / (full if k == "full_rate" else rates[k]["rate"]) for k, n in STEP_CLASSES.items())
+
+
+def valu_issue_main(args):
+    """The instruction-throughput leg: measured issue rates of the walk's
+    instruction forms on its launch shape, and the resulting ceiling of
+    photon-steps per second."""
+    import torch
+    from paper_2409_00165_amd import fos
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    stream = torch.cuda.current_stream()
+    rates = issue_rates(ctx.handle, stream)
+    t_step = issue_ceiling_step_time(rates)
+    full = max(FULL_RATE_FORMS, key=lambda k: rates[k]["rate"])
+    rec = {"metric": "VALU issue rate of the walk's instruction forms (lane-ops/s; Philox blocks/s)",
+           "value": rates[full]["rate"], "unit": f"lane-ops/s ({full}, the fastest full-rate form)", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": rates[full]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32/u32", "data": "synthetic",
+           "config": {"workload": "independent chains, CUs x 8 workgroups x 256 threads (the walk's launch shape)"},
+           "rates": rates, "step_classes": STEP_CLASSES, "ceiling_photon_steps_per_s": 1.0 / t_step,
+           "nominal_fp32_fma_lane_ops_per_s": VALU_PEAK, "gpu": _gpu_info(0)}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
 
 
 def cpu_baseline(wl, optics_host, seconds_target: float):
@@ -171,9 +244,17 @@ def sweep_main(args):
     say(f"GPU optics done for {I} items")
     fos.fos_mc_prepare(h, prob)
     say("prepared")
-    best, tune_ms = fos.fos_mc_autotune(h, seed=7, photon_cap=2000)
-    print(f"[bench] {I} items; autotuned launch {best} ({tune_ms:.2f} ms at 2000 photons/item)",
-          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if args.launch_json:
+        fos.fos_mc_set_launch(h, json.loads(args.launch_json))
+        best, tune_ms = fos.fos_mc_get_launch(h).as_dict(), float("nan")
+    else:
+        if args.tune_cache:
+            fos.fos_mc_autotune_cache(h, args.tune_cache)
+        best, tune_ms = fos.fos_mc_autotune(h, seed=7)
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] {I} items; autotuned launch {best} ({tune_ms:.2f} ms on the stratified sample, "
+          f"tuning {tune_s:.1f} s)", file=sys.stderr, flush=True)
     tal = torch.zeros(I * fos.N_TALLY, dtype=torch.int64, device=dev)
     fos.fos_mc_graph_capture(h, tal)
     say("graph captured")
@@ -204,7 +285,8 @@ def sweep_main(args):
         "data": "synthetic (seeded designs, analytic materials; optics on the GPU)",
         "config": {"workload": f"stacks_3layer: {args.designs} designs x 100 wavelengths, 3 layers on a "
                                "3.5+0.01i substrate, photons log-uniform 1e4..1e6 per design",
-                   "items": I, "photons_per_step": photons, "launch": best, "graph": True},
+                   "items": I, "photons_per_step": photons, "launch": best, "graph": True,
+                   "tuning_seconds": tune_s, "tuning_sample_ms": tune_ms},
         "photons_per_s": photons * args.steps / (sum(walk_ms) / 1e3),
         "design_spectra_per_s": args.designs * args.steps / (sum(walk_ms) / 1e3),
         "mean_steps_per_photon": steps_total / (photons * args.steps),
@@ -798,7 +880,7 @@ def main(argv=None):
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
     ap.add_argument("--workload", default="two_species_500",
                     choices=["two_species_500", "stacks_3layer", "surrogate", "surrogate_train", "paper_context",
-                             "weighted", "optics"],
+                             "weighted", "optics", "valu_issue"],
                     help="two_species_500 (default, the headline line; with the surrogate sweep as a sub-record), "
                          "stacks_3layer (batched sweep), surrogate (the committed ensemble: design sweep with Monte "
                          "Carlo fallback against plain Monte Carlo), surrogate_train (walk labels + training + "
@@ -818,6 +900,9 @@ def main(argv=None):
     ap.add_argument("--mc-designs", type=int, default=4096,
                     help="designs of the sweep timed with plain Monte Carlo (the first ones)")
     ap.add_argument("--no-surrogate", action="store_true", help="leave the surrogate sub-record out")
+    ap.add_argument("--tune-cache", default="", help="stacks_3layer: launch cache file of the autotuner")
+    ap.add_argument("--launch-json", default="",
+                    help="stacks_3layer: use this launch (JSON) instead of tuning")
     ap.add_argument("--tail-lanes", type=int, default=16,
                     help="label walks: tail_lanes launch knob (0 = the context default)")
     ap.add_argument("--label-state", default="", help="surrogate_train: resumable label state (.npz)")
@@ -841,6 +926,8 @@ def main(argv=None):
         return surrogate_main(args)
     if args.workload == "surrogate_train":
         return surrogate_train_main(args)
+    if args.workload == "valu_issue":
+        return valu_issue_main(args)
     if args.workload == "stacks_3layer":
         return sweep_main(args)
     if args.workload == "paper_context":
@@ -930,6 +1017,21 @@ def main(argv=None):
                      "work_per_step_slots": STEP_SLOTS, "steps_per_launch": steps_per_launch,
                      "kernel": "fos::walk", "kernel_hash": kernel_hash()},
     }
+    # the same walk against the measured issue rates of its own instruction
+    # forms, and its FP32 arithmetic against the FP32 FLOP peak
+    rates = issue_rates(h, stream)
+    t_ceiling = issue_ceiling_step_time(rates)
+    steps_per_s_kernel = steps_per_launch / walk_s
+    rec["roofline"]["measured_issue"] = {
+        "frac": steps_per_s_kernel * t_ceiling, "ceiling_photon_steps_per_s": 1.0 / t_ceiling,
+        "achieved_photon_steps_per_s": steps_per_s_kernel, "step_classes": STEP_CLASSES,
+        "rates": {k: v["rate"] for k, v in rates.items()},
+        "note": "frac = photon-steps/s of the walk x (seconds per photon-step at the measured rates of its "
+                "algorithmic instruction classes, one class after another)"}
+    flop_step = profile_value(VALU_FILE, "fp32_flop_per_photon_step")
+    rec["roofline"]["fp32_flop"] = None if flop_step is None else {
+        "flop_per_photon_step": flop_step, "achieved": flop_step * steps_per_s_kernel / 1e12,
+        "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": flop_step * steps_per_s_kernel / FP32_PEAK}
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         host = [o.cpu().numpy() for o in optics]

@@ -178,16 +178,30 @@ fos_status fos_mc_run(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed
 fos_status fos_mc_run_noalloc(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
                               const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
 
-/* Launch tuning for the prepared problem: walks at most `photon_cap`
- * photons of every item (0 = all) under a coordinate search over
- * refill_min x chunk x block_size x blocks_per_cu, times each candidate with
- * HIP events on `hip_stream` (best of two after a warm-up), and makes the
- * fastest the context's default.  Tallies do not depend on the launch
- * configuration, so tuning never changes results.  Synchronises the stream;
- * uses context-owned scratch.  best (HOST, may be NULL) receives the chosen
- * configuration and best_ms (HOST, may be NULL) its time. */
-fos_status fos_mc_autotune(fos_ctx* ctx, uint64_t seed, uint64_t photon_cap, fos_mc_launch* best,
+/* Launch tuning for the prepared problem.  The trial launches walk a sample
+ * of it: up to 2048 items chosen evenly from 16 strata of equal item count
+ * by an estimate of their walk length (photon-steps per photon from the
+ * layers' scattering and absorption depths and g, so the longest walks are
+ * in the sample), at their own photon budgets scaled by one common factor to
+ * at most `sample_photons` photons in all (0 = 2^30).  A coordinate search
+ * over refill_min x chunk x block_size x blocks_per_cu x tail_lanes times
+ * each candidate with HIP events on `hip_stream` (best of two after a
+ * warm-up) and makes the fastest the context's default.  With a launch
+ * cache set (fos_mc_autotune_cache), a problem whose class -- device
+ * architecture, layer slots, and the log2 of the item count, of the mean
+ * budget and of the photon-weighted mean walk estimate -- has an entry takes
+ * that launch without trials, and a tuned launch is written back under its
+ * class.  Tallies do not depend on the launch configuration, so tuning never
+ * changes results.  Synchronises the stream; uses context-owned scratch.
+ * best (HOST, may be NULL) receives the chosen configuration and best_ms
+ * (HOST, may be NULL) its time on the sample. */
+fos_status fos_mc_autotune(fos_ctx* ctx, uint64_t seed, uint64_t sample_photons, fos_mc_launch* best,
                            float* best_ms, void* hip_stream);
+
+/* Launch cache of fos_mc_autotune for this context: a JSON file (created if
+ * absent) of tuned launches keyed by (architecture, item class); NULL or ""
+ * turns it off.  The file is read and rewritten by each tuning call. */
+fos_status fos_mc_autotune_cache(fos_ctx* ctx, const char* path);
 
 /* Capture the execute sequence of the prepared problem (tally and cursor
  * reset, persistent walk) into a HIP graph owned by the context, writing to
@@ -434,6 +448,29 @@ fos_status fos_sweep_run(fos_ctx* ctx, const fos_mc_problem* problem, float spre
  * [lambdas] (normalised quadrature weights); out DEVICE float [2 designs]. */
 fos_status fos_spectral_reduce(fos_ctx* ctx, int32_t designs, int32_t lambdas, const float* rat, const float* w_r,
                                const float* w_e, float* out, void* hip_stream);
+
+/* Measurement hook: one launch of a kernel that issues one instruction form
+ * of the walk back to back on the walk's launch shape (CUs x 8 workgroups of
+ * 256 threads, 8 waves per SIMD), each thread running independent chains so
+ * that issue, not latency, sets the time: kind FOS_ISSUE_FMA (v_fma_f32),
+ * FOS_ISSUE_FMAC (v_fmac_f32, the accumulating encoding), FOS_ISSUE_MUL
+ * (v_mul_f32), FOS_ISSUE_RCP, _SQRT, _LOG, _COS (the step's transcendental
+ * forms) or FOS_ISSUE_PHILOX (whole Philox4x32-10 blocks, the walk's
+ * generator: 20 32x32->64 products and 20 three-input xors each).
+ * `iters` iterations per thread; sink DEVICE float [fos_issue_threads(ctx)]
+ * receives each thread's result; *ops (HOST) = instructions per lane summed
+ * over all lanes (Philox: blocks).  Asynchronous on `hip_stream`; time it with
+ * events on that stream. */
+#define FOS_ISSUE_FMA 0
+#define FOS_ISSUE_RCP 1
+#define FOS_ISSUE_SQRT 2
+#define FOS_ISSUE_LOG 3
+#define FOS_ISSUE_COS 4
+#define FOS_ISSUE_PHILOX 5
+#define FOS_ISSUE_FMAC 6
+#define FOS_ISSUE_MUL 7
+int64_t fos_issue_threads(const fos_ctx* ctx);
+fos_status fos_issue_run(fos_ctx* ctx, int32_t kind, int32_t iters, float* sink, uint64_t* ops, void* hip_stream);
 
 /* Raw Philox4x32-10 words for testing the generator: out[4*j + w] =
  * word w of counter (p lo, p hi, step, stream) with p = photon[j],

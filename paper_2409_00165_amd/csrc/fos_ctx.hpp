@@ -84,8 +84,16 @@ struct fos_ctx {
     unsigned int* nmax_dev = nullptr;        // device, 1 word
     unsigned long long* aux_host = nullptr;  // pinned host, 4 words
     // tuning and graph
+    std::string arch;                         // gcnArchName of the device
+    std::string tune_cache;                   // launch cache file (empty = none)
     unsigned long long* tune_tallies = nullptr;
     size_t tune_tallies_bytes = 0;
+    float4* tune_table = nullptr;             // the tuning sample's item records
+    size_t tune_table_bytes = 0;
+    unsigned long long* tune_prefix = nullptr;
+    size_t tune_prefix_bytes = 0;
+    unsigned char* tune_buf = nullptr;        // per-item cost and budget; sample indices and budgets
+    size_t tune_buf_bytes = 0;
     unsigned long long* seed_dev = nullptr;  // device, 1 word
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -119,6 +119,20 @@ size_t mie_order_bytes(int64_t n_units);
 hipError_t launch_mie_order(const OpticsArgs& a, int64_t n_units, void* buf, hipStream_t st);
 hipError_t launch_emt(const OpticsArgs& a, hipStream_t st);
 
+// launch tuner (tune_kernels.hip): estimated photon-steps per photon of every
+// item, and a rescaled sample of item records in a table of its own
+hipError_t launch_item_cost(const float4* table, int rf, int n, float* cost, uint64_t* photons, hipStream_t st);
+hipError_t launch_gather_records(const float4* table, int rf, const int32_t* idx, const uint64_t* photons, int m,
+                                 float4* out, hipStream_t st);
+
+// instruction-throughput kernels (issue_kernels.hip)
+enum IssueKind : int {
+    kIssueFma = 0, kIssueRcp = 1, kIssueSqrt = 2, kIssueLog = 3, kIssueCos = 4, kIssuePhilox = 5, kIssueFmac = 6,
+    kIssueMul = 7
+};
+int issue_ops_per_iteration(int kind);
+hipError_t launch_issue(int kind, int iters, int grid, int block, float* sink, hipStream_t st);
+
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
 hipError_t launch_reset(unsigned long long* tallies, unsigned long long* counter, int n_items, int nt,
                         hipStream_t st);

@@ -8,7 +8,11 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <numeric>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -141,6 +145,73 @@ unsigned char* scratch_of(int device)
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// --- launch cache of the tuner: a JSON object, one entry per (device
+// architecture, item class), each the tuned knobs and their time --------------
+struct CachedLaunch {
+    fos_mc_launch L{};
+    double ms = 0.0;
+};
+
+std::map<std::string, CachedLaunch> read_launch_cache(const std::string& path)
+{
+    std::map<std::string, CachedLaunch> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t pos = 0;
+    while ((pos = t.find('"', pos)) != std::string::npos) {
+        const size_t kend = t.find('"', pos + 1);
+        if (kend == std::string::npos) break;
+        const std::string key = t.substr(pos + 1, kend - pos - 1);
+        const size_t ob = t.find('{', kend), cb = t.find('}', kend);
+        if (ob == std::string::npos || cb == std::string::npos || cb < ob) break;
+        const std::string body = t.substr(ob + 1, cb - ob - 1);
+        auto field = [&](const char* name, double& v) {
+            const std::string pat = std::string("\"") + name + "\":";
+            const size_t p = body.find(pat);
+            if (p == std::string::npos) return false;
+            return std::sscanf(body.c_str() + p + pat.size(), "%lf", &v) == 1;
+        };
+        double bs, rm, ch, bpc, tl, ms;
+        if (field("block_size", bs) && field("refill_min", rm) && field("chunk", ch) &&
+            field("blocks_per_cu", bpc) && field("tail_lanes", tl) && field("ms", ms)) {
+            CachedLaunch e;
+            e.L.block_size = (int32_t)bs; e.L.refill_min = (int32_t)rm; e.L.chunk = (int32_t)ch;
+            e.L.blocks_per_cu = (int32_t)bpc; e.L.tail_lanes = (int32_t)tl;
+            e.ms = ms;
+            out[key] = e;
+        }
+        pos = cb + 1;
+    }
+    return out;
+}
+
+bool write_launch_cache(const std::string& path, const std::map<std::string, CachedLaunch>& entries)
+{
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return false;
+        f << "{\n";
+        size_t k = 0;
+        for (const auto& kv : entries) {
+            const fos_mc_launch& L = kv.second.L;
+            char buf[512];
+            std::snprintf(buf, sizeof buf,
+                          " \"%s\": {\"block_size\": %d, \"refill_min\": %d, \"chunk\": %d, \"blocks_per_cu\": %d, "
+                          "\"tail_lanes\": %d, \"ms\": %.4f}%s\n",
+                          kv.first.c_str(), L.block_size, L.refill_min, L.chunk, L.blocks_per_cu, L.tail_lanes,
+                          kv.second.ms, ++k < entries.size() ? "," : "");
+            f << buf;
+        }
+        f << "}\n";
+        if (!f) return false;
+    }
+    return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +245,7 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     if (!c) return FOS_E_OUT_OF_MEMORY;
     c->device = hip_device;
     c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     c->defaults.block_size = 256;
     c->defaults.refill_min = 8;
     c->defaults.chunk = 2048;
@@ -217,6 +289,9 @@ void fos_destroy(fos_ctx* c)
         if (c->mie_order) (void)hipFree(c->mie_order);
         if (c->ln_buf) (void)hipFree(c->ln_buf);
         if (c->tune_tallies) (void)hipFree(c->tune_tallies);
+        if (c->tune_table) (void)hipFree(c->tune_table);
+        if (c->tune_prefix) (void)hipFree(c->tune_prefix);
+        if (c->tune_buf) (void)hipFree(c->tune_buf);
         if (c->seed_dev) (void)hipFree(c->seed_dev);
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -395,8 +470,16 @@ fos_status fos_mc_weighted_fractions(fos_ctx* c, int32_t n, const uint64_t* tall
     return e == hipSuccess ? FOS_OK : hip_fail(c, e, "weighted fractions kernel");
 }
 
-fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_mc_launch* best,
-                           float* best_ms, void* hip_stream)
+fos_status fos_mc_autotune_cache(fos_ctx* c, const char* path)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    c->tune_cache = path ? path : "";
+    return FOS_OK;
+}
+
+fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t sample_photons, fos_mc_launch* best, float* best_ms,
+                           void* hip_stream)
 {
     if (!c) return FOS_E_INVALID_ARG;
     c->err.clear();
@@ -408,20 +491,108 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_m
     }
     DeviceGuard g(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    hipError_t e = grow(c->tune_tallies, c->tune_tallies_bytes,
-                        (size_t)c->n_items * fos::kNTally * sizeof(unsigned long long));
+    const int n = c->n_items, rf = fos::rec_f4(c->max_layers);
+    // 1. estimated photon-steps per photon and budget of every item
+    hipError_t e = grow(c->tune_buf, c->tune_buf_bytes, round256((size_t)n * sizeof(float)) + (size_t)n * 8);
     if (e != hipSuccess) return hip_fail(c, e, "tuning scratch");
+    float* d_cost = reinterpret_cast<float*>(c->tune_buf);
+    uint64_t* d_ph = reinterpret_cast<uint64_t*>(c->tune_buf + round256((size_t)n * sizeof(float)));
+    std::vector<float> cost(n);
+    std::vector<uint64_t> ph(n);
+    if ((e = fos::launch_item_cost(c->table, rf, n, d_cost, d_ph, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(cost.data(), d_cost, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ph.data(), d_ph, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "tuning estimates");
+    // the item class: layers, mean budget and photon-weighted mean walk
+    // length, each on a log2 scale
+    double sum_ph = 0.0, sum_steps = 0.0;
+    for (int i = 0; i < n; ++i) {
+        sum_ph += (double)ph[i];
+        sum_steps += (double)ph[i] * (double)cost[i];
+    }
+    const double mean_ph = sum_ph / n, mean_steps = sum_ph > 0 ? sum_steps / sum_ph : 1.0;
+    char key[256];
+    std::snprintf(key, sizeof key, "%s|L%d|I%d|N%d|S%d", c->arch.c_str(), c->max_layers,
+                  (int)std::lround(std::log2((double)n)), (int)std::lround(std::log2(std::max(mean_ph, 1.0))),
+                  (int)std::lround(std::log2(std::max(mean_steps, 1.0))));
+    if (!c->tune_cache.empty()) {
+        const auto cache = read_launch_cache(c->tune_cache);
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            fos_mc_launch L = c->defaults;
+            L.block_size = it->second.L.block_size; L.refill_min = it->second.L.refill_min;
+            L.chunk = it->second.L.chunk; L.blocks_per_cu = it->second.L.blocks_per_cu;
+            L.tail_lanes = it->second.L.tail_lanes;
+            if (check_launch(c, L) == FOS_OK) {
+                c->defaults = L;
+                c->chunk_set = true;
+                if (best) *best = L;
+                if (best_ms) *best_ms = (float)it->second.ms;
+                return FOS_OK;
+            }
+            c->err.clear();
+        }
+    }
+    // 2. the sample: kTuneItems items in kTuneStrata strata of equal item count
+    // by estimated walk length (longest walks included), at their own budgets
+    // scaled by one common factor to at most sample_photons in all
+    constexpr int kTuneItems = 2048, kTuneStrata = 16;
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] < cost[b]; });
+    const int m = std::min(n, kTuneItems), strata = std::min(m, kTuneStrata);
+    std::vector<int32_t> idx;
+    idx.reserve(m);
+    for (int s_ = 0; s_ < strata; ++s_) {
+        const size_t lo = (size_t)s_ * n / strata, hi = (size_t)(s_ + 1) * n / strata;
+        const int k = m / strata + (s_ < m % strata ? 1 : 0);
+        for (int j = 0; j < k; ++j) idx.push_back(order[lo + (size_t)j * (hi - lo) / k + (hi - lo) / (2 * k)]);
+    }
+    double total = 0.0;
+    for (int i : idx) total += (double)ph[i];
+    const double cap = sample_photons ? (double)sample_photons : (double)(1ull << 30);
+    const double f = total > cap ? cap / total : 1.0;
+    std::vector<uint64_t> sph(m);
+    for (int j = 0; j < m; ++j) {
+        const uint64_t N = ph[idx[j]];
+        sph[j] = N == 0 ? 0 : std::max<uint64_t>(1, (uint64_t)std::llround((double)N * f));
+    }
+    if ((e = grow(c->tune_table, c->tune_table_bytes, (size_t)m * rf * sizeof(float4))) != hipSuccess ||
+        (e = grow(c->tune_prefix, c->tune_prefix_bytes, ((size_t)m + 1) * sizeof(unsigned long long))) !=
+            hipSuccess ||
+        (e = grow(c->tune_tallies, c->tune_tallies_bytes, (size_t)m * fos::kNTally * sizeof(unsigned long long))) !=
+            hipSuccess)
+        return hip_fail(c, e, "tuning scratch");
+    // the sample's indices and budgets reuse the estimate buffers
+    int32_t* d_idx = reinterpret_cast<int32_t*>(c->tune_buf);
+    uint64_t* d_sph = d_ph;
+    if ((e = hipMemcpyAsync(d_idx, idx.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(d_sph, sph.data(), (size_t)m * sizeof(uint64_t), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = fos::launch_gather_records(c->table, rf, d_idx, d_sph, m, c->tune_table, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(c, e, "tuning sample");
+    // 3. one knob at a time from the current launch, each candidate timed
+    // three times on the sample (best of the last two)
     hipEvent_t ev0, ev1;
     if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
         return fail(c, FOS_E_DEVICE, "event creation failed");
     auto time_one = [&](const fos_mc_launch& L, float& ms) -> hipError_t {
         fos::WalkArgs a = walk_args(c, L, seed, c->tune_tallies);
-        a.photon_cap = photon_cap;
+        a.table = c->tune_table;
+        a.n_items = m;
+        a.chunk_prefix = c->tune_prefix;
         const int grid = c->n_cu * L.blocks_per_cu;
         float bestv = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipError_t r;
-            if ((r = enqueue_queue_reset(c, c->tune_tallies, L.chunk, photon_cap, st)) != hipSuccess) return r;
+            if ((r = fos::launch_reset(c->tune_tallies, c->chunk_counter, m, fos::kNTally, st)) != hipSuccess ||
+                (r = fos::launch_chunk_scan(c->tune_table, rf, m, L.chunk, 0, c->tune_prefix, st)) != hipSuccess)
+                return r;
             if ((r = hipEventRecord(ev0, st)) != hipSuccess) return r;
             if ((r = fos::launch_walk(a, grid, L.block_size, st)) != hipSuccess) return r;
             if ((r = hipEventRecord(ev1, st)) != hipSuccess) return r;
@@ -437,18 +608,20 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_m
     float cur_ms = 0.f;
     e = time_one(cur, cur_ms);
     const int32_t refills[] = {4, 6, 8, 12, 16};
-    const int32_t chunks[] = {1024, 2048, 4096, 8192};
+    const int32_t chunks[] = {512, 1024, 2048, 4096, 8192};
     const int32_t blocks[] = {128, 256, 512};
     const int32_t per_cu[] = {8, 16};
-    for (int knob = 0; knob < 4 && e == hipSuccess; ++knob) {
-        const int32_t* vals = knob == 0 ? refills : knob == 1 ? chunks : knob == 2 ? blocks : per_cu;
-        const int nv = knob == 0 ? 5 : knob == 1 ? 4 : knob == 2 ? 3 : 2;
+    const int32_t tails[] = {-1, 16};
+    for (int knob = 0; knob < 5 && e == hipSuccess; ++knob) {
+        const int32_t* vals = knob == 0 ? refills : knob == 1 ? chunks : knob == 2 ? blocks : knob == 3 ? per_cu : tails;
+        const int nv = knob == 0 ? 5 : knob == 1 ? 5 : knob == 2 ? 3 : 2;
         for (int i = 0; i < nv && e == hipSuccess; ++i) {
             fos_mc_launch L = cur;
             if (knob == 0) L.refill_min = vals[i];
             if (knob == 1) L.chunk = vals[i];
             if (knob == 2) L.block_size = vals[i];
             if (knob == 3) L.blocks_per_cu = vals[i];
+            if (knob == 4) L.tail_lanes = vals[i];
             if (std::memcmp(&L, &cur, sizeof L) == 0) continue;
             float ms = 0.f;
             e = time_one(L, ms);
@@ -462,6 +635,15 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t photon_cap, fos_m
     c->chunk_set = true;
     if (best) *best = cur;
     if (best_ms) *best_ms = cur_ms;
+    if (!c->tune_cache.empty()) {
+        auto cache = read_launch_cache(c->tune_cache);
+        CachedLaunch entry;
+        entry.L = cur;
+        entry.ms = cur_ms;
+        cache[key] = entry;
+        if (!write_launch_cache(c->tune_cache, cache))
+            return fail(c, FOS_E_INVALID_ARG, "cannot write the launch cache " + c->tune_cache);
+    }
     return FOS_OK;
 }
 
@@ -627,6 +809,23 @@ fos_status fos_mc_run_noalloc(fos_ctx* c, const fos_mc_problem* p, uint64_t seed
     a.tail_lanes = L.tail_lanes < 0 ? 0 : L.tail_lanes;
     if ((e = fos::launch_walk(a, c->n_cu * L.blocks_per_cu, L.block_size, st)) != hipSuccess)
         return hip_fail(c, e, "walk kernel");
+    return FOS_OK;
+}
+
+int64_t fos_issue_threads(const fos_ctx* c) { return c ? (int64_t)c->n_cu * 8 * 256 : 0; }
+
+fos_status fos_issue_run(fos_ctx* c, int32_t kind, int32_t iters, float* sink, uint64_t* ops, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    if (kind < FOS_ISSUE_FMA || kind > FOS_ISSUE_MUL) return fail(c, FOS_E_INVALID_ARG, "unknown issue kind");
+    if (iters < 1) return fail(c, FOS_E_INVALID_ARG, "iters must be >= 1");
+    if (!sink) return fail(c, FOS_E_INVALID_ARG, "sink is NULL");
+    DeviceGuard g(c->device);
+    const int grid = c->n_cu * 8, block = 256;
+    hipError_t e = fos::launch_issue(kind, iters, grid, block, sink, reinterpret_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(c, e, "issue kernel");
+    if (ops) *ops = (uint64_t)grid * block * (uint64_t)iters * (uint64_t)fos::issue_ops_per_iteration(kind);
     return FOS_OK;
 }
 

@@ -99,6 +99,10 @@ def lib():
         L.fos_mc_run_noalloc.argtypes = [c_void_p, POINTER(fos_mc_problem), c_uint64, POINTER(fos_mc_launch),
                                          c_void_p, c_void_p]
         L.fos_mc_run_noalloc.restype = c_int
+        L.fos_issue_threads.argtypes = [c_void_p]
+        L.fos_issue_threads.restype = ctypes.c_int64
+        L.fos_issue_run.argtypes = [c_void_p, c_int32, c_int32, c_void_p, POINTER(c_uint64), c_void_p]
+        L.fos_issue_run.restype = c_int
         L.fos_mc_prepared_items.argtypes = [c_void_p]
         L.fos_mc_prepared_items.restype = c_int32
         L.fos_mc_get_launch.argtypes = [c_void_p, POINTER(fos_mc_launch)]
@@ -108,6 +112,8 @@ def lib():
         L.fos_mc_autotune.argtypes = [c_void_p, c_uint64, c_uint64, POINTER(fos_mc_launch), POINTER(c_float),
                                       c_void_p]
         L.fos_mc_autotune.restype = c_int
+        L.fos_mc_autotune_cache.argtypes = [c_void_p, c_char_p]
+        L.fos_mc_autotune_cache.restype = c_int
         L.fos_mc_graph_capture.argtypes = [c_void_p, POINTER(fos_mc_launch), c_void_p, c_void_p]
         L.fos_mc_graph_capture.restype = c_int
         L.fos_mc_graph_launch.argtypes = [c_void_p, c_uint64, c_void_p]
@@ -292,13 +298,35 @@ def fos_mc_run_noalloc(ctx, problem: MCProblem, seed: int, tallies, launch=None,
                                          _ptr(tallies), _stream(stream)))
 
 
-def fos_mc_autotune(ctx, seed: int = 1, photon_cap: int = 0, stream=None):
-    """Tune the launch on the prepared problem; returns (launch dict, ms)."""
+ISSUE_KINDS = {"fma": 0, "rcp": 1, "sqrt": 2, "log": 3, "cos": 4, "philox": 5, "fmac": 6, "mul": 7}
+
+
+def fos_issue_threads(ctx) -> int:
+    return lib().fos_issue_threads(ctx)
+
+
+def fos_issue_run(ctx, kind: str, iters: int, sink, stream=None) -> int:
+    """One launch of the instruction-throughput kernel `kind`; returns the
+    lane operations (Philox: blocks) it issues."""
+    import torch
+    ops = c_uint64()
+    _check(ctx, lib().fos_issue_run(ctx, ISSUE_KINDS[kind], iters, _ptr(sink, torch.float32, fos_issue_threads(ctx)),
+                                    ctypes.byref(ops), _stream(stream)))
+    return ops.value
+
+
+def fos_mc_autotune(ctx, seed: int = 1, sample_photons: int = 0, stream=None):
+    """Tune the launch on a stratified sample of the prepared problem;
+    returns (launch dict, ms on the sample)."""
     best = fos_mc_launch()
     ms = c_float()
-    _check(ctx, lib().fos_mc_autotune(ctx, c_uint64(seed), c_uint64(photon_cap), ctypes.byref(best),
+    _check(ctx, lib().fos_mc_autotune(ctx, c_uint64(seed), c_uint64(sample_photons), ctypes.byref(best),
                                       ctypes.byref(ms), _stream(stream)))
     return best.as_dict(), ms.value
+
+
+def fos_mc_autotune_cache(ctx, path) -> None:
+    _check(ctx, lib().fos_mc_autotune_cache(ctx, (path or "").encode()))
 
 
 def fos_mc_graph_capture(ctx, tallies, launch=None, stream=None) -> None:

@@ -49,11 +49,43 @@ def test_autotune_picks_a_valid_launch_and_keeps_results(ctx, torch):
     prob = device_problem(a)
     ref = run_gpu(ctx, a, 99)
     fos.fos_mc_prepare(ctx, prob)
-    best, ms = fos.fos_mc_autotune(ctx, seed=5, photon_cap=5000)
+    best, ms = fos.fos_mc_autotune(ctx, seed=5, sample_photons=200_000)
     print("autotune:", best, f"{ms:.3f} ms", flush=True)
     assert best["block_size"] % 64 == 0 and 1 <= best["refill_min"] <= 64 and ms > 0
+    assert best["tail_lanes"] in (-1, 16)
     assert fos.fos_mc_get_launch(ctx).as_dict() == best
     assert (run_gpu(ctx, a, 99) == ref).all()
+
+
+def test_autotune_cache_serves_the_class_it_was_tuned_on(torch, tmp_path):
+    """The tuned launch is written to the cache under the problem's class; a
+    second context with the same cache takes it for a problem of that class
+    without trial launches (the recorded time comes back), and a problem of
+    another class is tuned afresh and added."""
+    import json
+    from paper_2409_00165_amd import fos
+    from gpu_helpers import device_problem
+    path = str(tmp_path / "launches.json")
+    a = _det_problem()
+    with fos.Context(0) as c1:
+        fos.fos_mc_autotune_cache(c1.handle, path)
+        fos.fos_mc_prepare(c1.handle, device_problem(a))
+        best, ms = fos.fos_mc_autotune(c1.handle, seed=5, sample_photons=100_000)
+    cache = json.load(open(path))
+    assert len(cache) == 1
+    (key, entry), = cache.items()
+    assert key.startswith("gfx950") and "|L3|" in key
+    assert {k: entry[k] for k in best if k in entry} == {k: v for k, v in best.items() if k in entry}
+    with fos.Context(0) as c2:
+        fos.fos_mc_autotune_cache(c2.handle, path)
+        fos.fos_mc_prepare(c2.handle, device_problem(a))
+        best2, ms2 = fos.fos_mc_autotune(c2.handle, seed=9, sample_photons=100_000)
+        assert best2 == best and abs(ms2 - entry["ms"]) < 1e-3
+        assert (run_gpu(c2.handle, a, 99) == run_gpu(c2.handle, a, 99, launch=best)).all()
+        b = make_arrays(np.full((20, 1), 2.0), 0.05, 0.7, 1.5, 10.0, photons=50_000)
+        fos.fos_mc_prepare(c2.handle, device_problem(b))
+        fos.fos_mc_autotune(c2.handle, seed=9, sample_photons=100_000)
+    assert len(json.load(open(path))) == 2
 
 
 def test_graph_sweep_replays_any_seed(ctx, torch):
@@ -90,8 +122,8 @@ def test_batched_three_layer_designs_full_budgets(ctx, torch):
     prob = _device_problem_with_gpu_optics(ctx, torch, wl)
     I = prob.n_items
     fos.fos_mc_prepare(ctx, prob)
-    best, ms = fos.fos_mc_autotune(ctx, seed=7, photon_cap=2000)
-    print("autotuned launch", best, f"{ms:.2f} ms", flush=True)
+    best, ms = fos.fos_mc_autotune(ctx, seed=7)
+    print("autotuned launch", best, f"{ms:.2f} ms on the sample", flush=True)
     tal = torch.zeros(I * 6, dtype=torch.int64, device="cuda")
     fos.fos_mc_graph_capture(ctx, tal)
     fos.fos_mc_graph_launch(ctx, GPU_SEED)

@@ -191,6 +191,62 @@ def valu_issue_main(args):
     return 0
 
 
+LONE_CAPS = (30_000, 100_000)
+LONE_TAILS = (-1, 16, 64)
+
+
+def lone_step_main(args):
+    """Latency of one photon-step on a lone lane, the step time of a launch's
+    tail: 64 photons, one per wave (chunk 1), in a slab of optical thickness
+    1e7 that none of them leaves before the step cap, run at two caps; the
+    time difference over the cap difference is one step of one lane.  Two
+    phase functions (forward-peaked g = 0.99999 and isotropic g = 0), each
+    with the tail phase off (-1) and on (16 and 64 lanes)."""
+    import torch
+    from paper_2409_00165_amd import fos
+    torch.cuda.set_device(0)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    one = lambda v: np.array([[v]], np.float64)
+    out = {}
+    for name, g in (("forward_g0.99999", 0.99999), ("isotropic_g0", 0.0)):
+        prob = fos.MCProblem.from_numpy("cuda", np.array([1], np.int32), one(1e5), one(1e-12), one(g), one(1.0),
+                                        one(100.0), np.array([1.0]), np.array([1.0]), np.array([0.0]),
+                                        np.array([1.0]), np.array([64], np.int64))
+        fos.fos_mc_prepare(h, prob)
+        for tail in LONE_TAILS:
+            res = {}
+            for cap in LONE_CAPS:
+                best, tal = None, None
+                for _ in range(3):
+                    t = torch.zeros(6, dtype=torch.int64, device="cuda")
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    fos.fos_mc_execute(h, 5, t, launch={"tail_lanes": tail, "max_steps": cap, "chunk": 1,
+                                                        "refill_min": 1})
+                    b.record()
+                    b.synchronize()
+                    ms = a.elapsed_time(b)
+                    best = ms if best is None else min(best, ms)
+                    tal = t.cpu().tolist()
+                res[cap] = {"ms": best, "capped": tal[4], "steps": tal[5]}
+            lo, hi = LONE_CAPS
+            us = (res[hi]["ms"] - res[lo]["ms"]) / (hi - lo) * 1e3
+            out[f"{name}/tail{tail}"] = {"us_per_step": us, "runs": {str(k): v for k, v in res.items()}}
+            print(f"[bench] {name} tail_lanes {tail}: {us:.4f} us per lone step", file=sys.stderr, flush=True)
+    key = "forward_g0.99999/tail16"
+    rec = {"metric": "latency of one photon-step on a lone lane", "value": out[key]["us_per_step"],
+           "unit": "us/step (forward-peaked, tail_lanes 16)", "n_gpus": 1, "steps": 3, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 photons, one per wave, slab tau 1e7 (mu_s 1e5, d 100, mu_a 1e-12, n 1), "
+                                  f"caps {LONE_CAPS[0]} and {LONE_CAPS[1]}"},
+           "cases": out, "gpu": _gpu_info(0)}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def cpu_baseline(wl, optics_host, seconds_target: float):
     """FP64 oracle on every 10th wavelength; photons sized for ~target s."""
     import oracle
@@ -880,14 +936,16 @@ def main(argv=None):
     ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
     ap.add_argument("--workload", default="two_species_500",
                     choices=["two_species_500", "stacks_3layer", "surrogate", "surrogate_train", "paper_context",
-                             "weighted", "optics", "valu_issue"],
+                             "weighted", "optics", "valu_issue", "lone_step"],
                     help="two_species_500 (default, the headline line; with the surrogate sweep as a sub-record), "
                          "stacks_3layer (batched sweep), surrogate (the committed ensemble: design sweep with Monte "
                          "Carlo fallback against plain Monte Carlo), surrogate_train (walk labels + training + "
                          "held-out error; writes the model) or "
                          "paper_context (a run shaped like the paper's desktop timing, GPU and oracle) or "
                          "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency) or "
-                         "optics (per-entry GPU Mie + effective medium: homogeneous, coated, spread)")
+                         "optics (per-entry GPU Mie + effective medium: homogeneous, coated, spread) or "
+                         "valu_issue (issue rates of the walk's instruction forms) or "
+                         "lone_step (step latency of a lone lane, tail phase off and on)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-photons", type=int, default=100_000)
     ap.add_argument("--epochs", type=int, default=60)
@@ -928,6 +986,8 @@ def main(argv=None):
         return surrogate_train_main(args)
     if args.workload == "valu_issue":
         return valu_issue_main(args)
+    if args.workload == "lone_step":
+        return lone_step_main(args)
     if args.workload == "stacks_3layer":
         return sweep_main(args)
     if args.workload == "paper_context":

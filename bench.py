@@ -500,6 +500,11 @@ def surrogate_train_main(args):
     def say(msg):
         print(f"[bench] {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
 
+    # the labelling launches in flight each take a stream: give the process
+    # that many hardware queues (HIP reads this when it starts, below), so
+    # that their kernels do not wait behind each other in a shared queue
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < args.label_in_flight:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.label_in_flight, 32))
     import hashlib
     import torch
     from paper_2409_00165_amd import fos
@@ -508,7 +513,7 @@ def surrogate_train_main(args):
     ctx = fos.Context(0)
     h = ctx.handle
     say("surrogate training pipeline start")
-    launch = {"tail_lanes": args.tail_lanes} if args.tail_lanes else None
+    launch = {k: v for k, v in (("tail_lanes", args.tail_lanes), ("regroup_lanes", args.regroup_lanes)) if v} or None
     n_tr = args.train_samples
     if args.load_data:
         # stored labels, re-joined to features regenerated from the same item seeds
@@ -550,7 +555,8 @@ def surrogate_train_main(args):
                          state=json.dumps(dict(st, seconds=st["seconds"] + time.perf_counter() - t_call)))
 
         x, y, steps, secs = SP.make_training_set(h, n_tr, args.train_photons, seed=TRAIN_SEED, log=say,
-                                                 launch=launch, launches=todo, y=y, on_launch=on_launch)
+                                                 launch=launch, launches=todo, y=y, on_launch=on_launch,
+                                                 in_flight=args.label_in_flight)
         st["seconds"] += secs
         if len(st["done"]) < len(sizes):
             left = [c for c in range(len(sizes)) if c not in st["done"]]
@@ -561,9 +567,23 @@ def surrogate_train_main(args):
         rec = {"samples": n_tr, "photons_each": args.train_photons, "label_seconds": st["seconds"],
                "label_photon_steps": st["steps"], "label_photon_steps_per_s": st["steps"] / st["seconds"],
                "label_capped_photons": st["capped"], "label_launches": len(sizes),
-               "label_launch": launch or "default"}
+               "label_launch": launch or "default", "label_in_flight": args.label_in_flight,
+               "label_launch_seconds": st["launch_seconds"]}
         say(f"labels: {n_tr} items x {args.train_photons} photons in {st['seconds']:.1f} s of walks, "
             f"{st['steps']:.3e} photon-steps, {st['capped']} capped photons")
+        if args.labels_only:
+            line = {"metric": "surrogate training labels (walk only)", "value": st["seconds"], "unit": "s",
+                    "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * st["seconds"],
+                    "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32 walk",
+                    "data": "synthetic",
+                    "config": {"workload": f"{n_tr} single-layer training items x {args.train_photons} photons, "
+                                           f"longest first in {len(sizes)} launches, {args.label_in_flight} "
+                                           "in flight"},
+                    "labels": rec, "label_checksum": float(y.double().sum().item()),
+                    "wall_s": time.perf_counter() - t_start}
+            ctx.close()
+            print(json.dumps(line), flush=True)
+            return 0
     xh, yh, _, _ = SP.make_training_set(h, HELD_N, rec["photons_each"], seed=HELD_SEED, chunk=HELD_N, launch=launch)
     if args.save_data:
         np.savez(args.save_data, y=y.cpu().numpy(), yh=yh.cpu().numpy(), n=n_tr,
@@ -963,6 +983,11 @@ def main(argv=None):
                     help="stacks_3layer: use this launch (JSON) instead of tuning")
     ap.add_argument("--tail-lanes", type=int, default=16,
                     help="label walks: tail_lanes launch knob (0 = the context default)")
+    ap.add_argument("--regroup-lanes", type=int, default=32,
+                    help="label walks: regroup_lanes launch knob (0 = the context default, -1 = off)")
+    ap.add_argument("--label-in-flight", type=int, default=8, help="label walks: launches in flight")
+    ap.add_argument("--labels-only", action="store_true",
+                    help="surrogate_train: walk the labels, report their time, and stop (no training or model)")
     ap.add_argument("--label-state", default="", help="surrogate_train: resumable label state (.npz)")
     ap.add_argument("--label-launches", default="", help="surrogate_train: walk only launches a:b of the labels")
     ap.add_argument("--save-data", default="", help="write the walk-labelled training and held-out sets (.npz)")

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define FOS_ABI_VERSION 3
+#define FOS_ABI_VERSION 4
 #define FOS_MAX_LAYERS 8
 
 /* tally slots per item, in this order, uint64 each */
@@ -132,7 +132,15 @@ typedef struct {
                                random draws on all 64 lanes ahead of the steps
                                that use them (a build of the walk with that
                                phase); -1: the build without it; 1..64, -1     */
-    int32_t reserved;       /* must be 0                                          */
+    int32_t regroup_lanes;  /* > 0: regrouping in the tail build of the walk.  A
+                               wave with no photons left to claim and at most this
+                               many in flight writes their state to a hand-off
+                               list in HBM and leaves, and waves with idle lanes
+                               take them over, while more than one wave per SIMD
+                               is alive; -1: off; 1..32, -1.  Needs a context
+                               hand-off list of (CUs x blocks_per_cu x waves per
+                               block x regroup_lanes) records of 32 B (48 B
+                               weighted) plus 4 B each, grown on first use       */
 } fos_mc_launch;
 
 /* Validate `problem` and pack it into the context's device item table
@@ -148,9 +156,12 @@ fos_status fos_mc_prepare(fos_ctx* ctx, const fos_mc_problem* problem, void* hip
  * `tallies` is DEVICE uint64 [n_items * FOS_N_TALLY], overwritten.  The
  * random stream of photon p of item i under `seed` is Philox4x32-10 with
  * counter (p lo, p hi, step, i) and key (seed lo, seed hi), so tallies are
- * bit-identical for every launch configuration, chunking and scheduling.
- * Asynchronous on `hip_stream`; allocates nothing, never synchronises, and
- * may be captured into a HIP graph.  `launch` may be NULL. */
+ * bit-identical for every launch configuration, chunking, scheduling and
+ * hand-off between waves.  Asynchronous on `hip_stream`; never synchronises,
+ * and may be captured into a HIP graph.  It allocates nothing, except that a
+ * launch with regroup_lanes > 0 grows the context's hand-off list the first
+ * time it needs more (do one such call before capturing one).  `launch` may
+ * be NULL. */
 fos_status fos_mc_execute(fos_ctx* ctx, uint64_t seed, const fos_mc_launch* launch,
                           uint64_t* tallies, void* hip_stream);
 
@@ -173,7 +184,8 @@ fos_status fos_mc_run(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed
  * calls that overlap on one GPU (other threads, other contexts, or another
  * stream before this call's walk has finished) race and give wrong tallies.
  * Validation synchronises `hip_stream` once, as fos_mc_prepare does; the
- * walk is then asynchronous on it. */
+ * walk is then asynchronous on it.  A launch with regroup_lanes > 0 is
+ * rejected (its hand-off list is a context allocation). */
 #define FOS_NOALLOC_SCRATCH_BYTES (16u << 20)
 fos_status fos_mc_run_noalloc(fos_ctx* ctx, const fos_mc_problem* problem, uint64_t seed,
                               const fos_mc_launch* launch, uint64_t* tallies, void* hip_stream);
@@ -202,6 +214,15 @@ fos_status fos_mc_autotune(fos_ctx* ctx, uint64_t seed, uint64_t sample_photons,
  * absent) of tuned launches keyed by (architecture, item class); NULL or ""
  * turns it off.  The file is read and rewritten by each tuning call. */
 fos_status fos_mc_autotune_cache(fos_ctx* ctx, const char* path);
+
+/* Hand-off counts of the last regrouping walk (regroup_lanes > 0) on this
+ * context: photons handed from one wave to another (HOST, may be NULL) and
+ * hand-offs whose record a taking wave did not see written within its wait
+ * bound (HOST, may be NULL; each such photon is missing from the tallies, so
+ * anything but 0 means those tallies are short).  Both 0 before any
+ * regrouping walk.  Synchronises `hip_stream`, which must order the call
+ * after that walk. */
+fos_status fos_mc_handoff_counts(fos_ctx* ctx, uint64_t* handed, uint64_t* lost, void* hip_stream);
 
 /* Capture the execute sequence of the prepared problem (tally and cursor
  * reset, persistent walk) into a HIP graph owned by the context, writing to

@@ -94,6 +94,9 @@ struct fos_ctx {
     size_t tune_prefix_bytes = 0;
     unsigned char* tune_buf = nullptr;        // per-item cost and budget; sample indices and budgets
     size_t tune_buf_bytes = 0;
+    unsigned char* hand_buf = nullptr;        // hand-off list of regrouping walks
+    size_t hand_buf_bytes = 0;
+    unsigned char* graph_hand = nullptr;      // the list a captured regrouping graph uses
     unsigned long long* seed_dev = nullptr;  // device, 1 word
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

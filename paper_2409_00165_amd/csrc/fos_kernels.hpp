@@ -47,7 +47,25 @@ struct WalkArgs {
     int tail_lanes;               // > 0: the build of the walk with the tail phase; a wave with no
                                   // chunk left and at most this many photons in flight prepares
                                   // their draws on all its lanes (0 = the build without it)
+    // regrouping (the tail build's drain phase): a wave with no chunk left and
+    // at most regroup_lanes photons in flight hands them off through the list
+    // below while more than regroup_min_waves waves are alive (0 = off)
+    int regroup_lanes;
+    int regroup_min_waves;
+    // the hand-off list, one allocation: [4] control words (reserved, taken,
+    // waves alive, timed-out takes), padded to 256 B; [hand_cap] ready flags,
+    // padded to 256 B; [hand_cap][2 or 3] float4 records
+    unsigned char* hand;
+    uint32_t hand_cap;            // records: waves of the launch x regroup_lanes
 };
+
+// byte offsets of the parts of the hand-off list
+__host__ __device__ inline size_t hand_flags_offset() { return 256; }
+__host__ __device__ inline size_t hand_records_offset(uint64_t cap) { return 256 + ((cap * 4 + 255) / 256) * 256; }
+__host__ __device__ inline size_t hand_bytes(uint64_t cap, bool weighted)
+{
+    return hand_records_offset(cap) + cap * (weighted ? 3 : 2) * 16;
+}
 
 enum OptErrCode : int {
     kOptErrLambda = 1,
@@ -140,6 +158,8 @@ hipError_t launch_chunk_scan(const float4* table, int rec_f4, int n_items, int c
                              unsigned long long* prefix, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t st);
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted = false);
+// clears the hand-off list of a regrouping walk (nothing when regroup_lanes <= 0)
+hipError_t launch_reset_handoff(const WalkArgs& a, hipStream_t st);
 hipError_t launch_fractions(int n, const unsigned long long* tallies, float* rat, hipStream_t st);
 hipError_t launch_weighted_fractions(int n, const unsigned long long* tallies, float* rat, float* se, hipStream_t st);
 size_t walk_lds_bytes(int block_size, int max_layers, bool weighted = false, bool tail = false);

@@ -118,6 +118,17 @@ __global__ void reset_run(unsigned long long* tallies, unsigned long long* count
     if (tid == 0) *counter = 0ull;
 }
 
+// Clear the hand-off list of a regrouping walk: its control words and the
+// ready flag of every record.
+__global__ void reset_handoff(unsigned char* hand, uint64_t cap)
+{
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    unsigned int* flags = reinterpret_cast<unsigned int*>(hand + hand_flags_offset());
+    for (size_t j = tid; j < cap; j += stride) flags[j] = 0u;
+    if (tid < 4) reinterpret_cast<unsigned long long*>(hand)[tid] = 0ull;
+}
+
 // Exclusive prefix of per-item chunk counts ceil(min(N, cap) / chunk), one
 // block of 1024 threads: each thread sums a contiguous run of items, the run
 // totals are scanned in LDS, and a second pass writes the prefix.
@@ -188,6 +199,16 @@ __device__ __forceinline__ void load_layer(const float4* slot_rec, int l, LaneLa
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// A 64-bit value of the first active lane, made wave-uniform.  The builtin
+// returns a signed int: each half goes through uint32_t so that the low
+// half is not sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
 __device__ __forceinline__ int lane_rank(uint64_t mask)
 {
     // number of set bits of mask below this lane
@@ -207,6 +228,68 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
     return (unsigned long long)__double2ull_rn(w * kWeightUnit);
 }
 
+// A finished photon's outcome, step count and (weighted form) weights added
+// to its item's counters `c0` (LDS slot or HBM tallies).
+template <bool WEIGHTED>
+__device__ __forceinline__ void finish_photon(unsigned long long* c0, int term, uint32_t k, float wgt, float absd)
+{
+    if constexpr (WEIGHTED) {
+        atomicAdd(c0 + kWSteps, (unsigned long long)k);
+        const double ad = (double)absd;
+        if (ad > 0.0) {
+            atomicAdd(c0 + kWAbs, weight_units(ad));
+            atomicAdd(c0 + kWAbs2, weight_units(ad * ad));
+        }
+        if (term == kTrans || term == kRDiff) {
+            const double w = (double)wgt;
+            atomicAdd(c0 + (term == kTrans ? kWTrans : kWRDiff), weight_units(w));
+            atomicAdd(c0 + (term == kTrans ? kWTrans2 : kWRDiff2), weight_units(w * w));
+        } else if (term == kWRoulette) {
+            atomicAdd(c0 + kWRoulette, 1ull);
+        } else if (term == kCap) {
+            atomicAdd(c0 + kWCap, 1ull);
+        }
+    } else {
+        atomicAdd(c0 + kSteps, (unsigned long long)k);
+        atomicAdd(c0 + term, 1ull);
+    }
+}
+
+// Hand-off list control words (WalkArgs::hand_ctl): records reserved and
+// records taken so far, waves of the launch alive, takes that timed out.
+constexpr int kHandReserved = 0, kHandClaimed = 1, kHandWaves = 2, kHandLost = 3;
+constexpr int kAbsorbEvery = 4;       // drain rounds before the first look again at an empty list
+constexpr int kAbsorbMax = 128;       // and at most this many
+constexpr int kHandRetry = 8;         // drain rounds before a refused hand-off is tried again
+constexpr int kHandSpins = 1 << 22;   // bound on the wait for a reserved record's flag
+
+// The counters are read and updated with relaxed device-scope atomics; a
+// record's contents are ordered by its flag (release store, acquire load),
+// and the live-wave count's acquire-release updates order every hand-off
+// before the last wave's final look at the counters.
+__device__ __forceinline__ unsigned long long hand_load(unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A wave with nothing in flight leaves the launch: true when it may exit.
+// The wave whose leaving takes the live-wave count to zero looks at the
+// list once more and, if photons are still listed, stays to take them (every
+// hand-off is written and flagged before its wave leaves).
+__device__ __forceinline__ bool wave_leave(unsigned long long* ctl, int lane)
+{
+    int stay = 0;
+    if (lane == 0) {
+        const unsigned long long old = __hip_atomic_fetch_add(ctl + kHandWaves, ~0ull, __ATOMIC_ACQ_REL,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 1ull && hand_load(ctl + kHandClaimed) < hand_load(ctl + kHandReserved)) {
+            __hip_atomic_fetch_add(ctl + kHandWaves, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            stay = 1;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(stay) == 0;
+}
+
 // WEIGHTED selects the weighted-packet (MCML) form: no specular or albedo
 // draws; the packet deposits mu_a/mu_t of its weight at each interaction,
 // always scatters, plays roulette below kRouletteThreshold, and tallies
@@ -216,9 +299,10 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
 // compiled in.
 // One photon-step of a lane from its Philox block X (the lane's step
 // counter k already advanced): free path, then boundary or interaction;
-// sets `term` when the photon ends.  Written out as a macro so that each
-// loop of the walk compiles it in place.
-#define FOS_WALK_STEP(X)                                                                     \
+// sets `term` when the photon ends.  REC is the lane's item record (its LDS
+// slot, or the item table in HBM after a hand-off).  Written out as a macro
+// so that each loop of the walk compiles it in place.
+#define FOS_WALK_STEP(X, REC)                                                                \
     do {                                                                                     \
         const uint4 x_ = (X);                                                                \
         const float U1 = u24(x_.y);                                                          \
@@ -241,7 +325,7 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
                 const bool matched = down ? (fl & kMatchDn) : (fl & kMatchUp);               \
                 float R = 0.f, ct = aa;                                                      \
                 if (down && (fl & kComplexDn)) {                                             \
-                    const float4 h0 = tab[slot * rf];                                        \
+                    const float4 h0 = (REC)[0];                                              \
                     R = fresnel_complex(aa, P.n, h0.z, h0.w);                                \
                 } else if (!matched) {                                                       \
                     const float m = down ? P.m_dn : P.m_up;                                  \
@@ -259,7 +343,7 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
                     term = down ? kTrans : kRDiff;                                           \
                 } else {                                                                     \
                     layer += down ? 1 : -1;                                                  \
-                    load_layer(tab + slot * rf, layer, P);                                   \
+                    load_layer((REC), layer, P);                                             \
                     uz = down ? ct : -ct;                                                    \
                     z = down ? 0.f : P.thick;                                                \
                 }                                                                            \
@@ -297,9 +381,10 @@ __device__ __forceinline__ unsigned long long weight_units(double w)
         }                                                                                    \
     } while (0)
 
-// TAIL is the build for heavy-tailed runs: it adds the tail phase below (a
-// wave that has nothing left to claim and at most tail_lanes photons in
-// flight prepares their next draws on all 64 lanes).
+// TAIL is the build for heavy-tailed runs: once a wave has nothing left to
+// claim it enters the drain phase below, where photons can be handed between
+// waves (regroup_lanes) and few photons in flight get their draws prepared
+// on all 64 lanes (tail_lanes).
 template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE, bool TAIL>
 __device__ __forceinline__ void walk_body(WalkArgs a)
 {
@@ -315,13 +400,27 @@ __device__ __forceinline__ void walk_body(WalkArgs a)
     int* slot_item = reinterpret_cast<int*>(reinterpret_cast<unsigned long long*>(
                          smem + (size_t)nwaves * kSlots * rf) + (size_t)nwaves * kSlots * NT) +
                      wv * kSlots;                                            // [kSlots]
-    // tail phase: 64 prepared Philox blocks of this wave
-    uint4* drw = reinterpret_cast<uint4*>(smem + (size_t)nwaves * kSlots * rf +
-                                          (size_t)nwaves * kSlots * NT / 2 + (size_t)nwaves * kSlots / 4) +
-                 (size_t)wv * 64;
+    // tail build: 64 prepared Philox blocks of this wave, then the wave's copy
+    // of the hand-off arguments (list address, capacity, regroup_lanes and
+    // regroup_min_waves), read back at the drain so that they do not occupy
+    // scalar registers through the main loop
+    uint4* const drw0 = reinterpret_cast<uint4*>(smem + (size_t)nwaves * kSlots * rf +
+                                                 (size_t)nwaves * kSlots * NT / 2 + (size_t)nwaves * kSlots / 4);
+    uint4* drw = drw0 + (size_t)wv * 64;
+    uint4* harg = drw0 + (size_t)nwaves * 64 + wv;
 
     for (int j = lane; j < kSlots * NT; j += 64) cnt[j] = 0ull;
     if (lane < kSlots) slot_item[lane] = -1;
+    if constexpr (TAIL) {
+        if (lane == 0) {
+            const uint64_t hp = reinterpret_cast<uint64_t>(a.hand);
+            *harg = make_uint4((uint32_t)hp, (uint32_t)(hp >> 32), a.hand_cap,
+                               (uint32_t)a.regroup_lanes | ((uint32_t)a.regroup_min_waves << 8));
+            if (a.regroup_lanes > 0)
+                __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(a.hand) + kHandWaves, 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     wave_sync_lds();
 
     const uint64_t seed = a.seed_ptr ? *a.seed_ptr : a.seed;
@@ -372,10 +471,8 @@ __device__ __forceinline__ void walk_body(WalkArgs a)
                     }
                 }
                 c_item = __builtin_amdgcn_readfirstlane(c_item);
-                c_start = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c_start >> 32)) << 32) |
-                          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)c_start);
-                c_end = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c_end >> 32)) << 32) |
-                        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)c_end);
+                c_start = uniform_u64(c_start);
+                c_end = uniform_u64(c_end);
                 if (c_item < 0) { queue_done = true; break; }
                 if (c_item != src_item) {
                     // recycle slot ns: flush its counts, stage the new item
@@ -442,82 +539,18 @@ __device__ __forceinline__ void walk_body(WalkArgs a)
             dead = ballot64(!alive);
         }
         if (dead == ~0ull) break;   // queue exhausted and nothing in flight
+        if constexpr (TAIL) {
+            if (queue_done && src_next >= src_end) break;   // nothing left to claim: drain phase
+        }
 
         // ---------------- walk ----------------
-
-        if constexpr (TAIL) {
-            // ---- tail: nothing left to claim and few photons in flight ----
-            // A step's Philox block depends only on (photon, step, item,
-            // seed), so the idle lanes compute the next draws of the live
-            // photons ahead of time: with nl photons in flight each gets
-            // B = 64 / 2^ceil(log2 nl) consecutive blocks, one per lane, in
-            // the wave's LDS buffer, and its lane reads the block of each
-            // step there instead of running the ten dependent Philox rounds.
-            // The draws, and so the tallies, are the same bits.
-            if (queue_done && src_next >= src_end && 64 - __popcll(dead) <= a.tail_lanes) {
-                const uint64_t live = ballot64(alive && k < max_steps);
-                const int nl = __popcll(live);
-                int lg = 0;
-                while ((1 << lg) < nl) ++lg;
-                const int B = 64 >> lg;
-                {
-                    // this lane prepares draw o of the q-th photon in flight
-                    const int q = lane >> (6 - lg);
-                    const int o = lane & (B - 1);
-                    uint64_t m = live;
-                    for (int t = 0; t < q && m; ++t) m &= m - 1;
-                    const int src = m ? (int)__builtin_ctzll(m) : 0;
-                    const uint32_t sp_lo = __shfl(p_lo, src), sp_hi = __shfl(p_hi, src);
-                    const uint32_t s_k = __shfl(k, src), s_item = __shfl(item, src);
-                    drw[lane] = philox4x32_10(sp_lo, sp_hi, s_k + 1u + (uint32_t)o, s_item, k0, k1);
-                }
-                wave_sync_lds();
-                const int base = (alive && k < max_steps) ? (lane_rank(live) << (6 - lg)) : 0;
-                for (int j = 0; j < B; ++j) {
-                    const bool go = alive && k < max_steps;
-                    int term = (alive && !go) ? (int)kCap : -1;
-                    if (go) {
-                        ++k;
-                        FOS_WALK_STEP(drw[base + j]);
-                    }
-                    if (term >= 0) {
-                        // this lane's photon finished: tallies as in the loop below
-                        alive = false;
-                        unsigned long long* c0 = cnt + slot * NT;
-                        if constexpr (WEIGHTED) {
-                            atomicAdd(c0 + kWSteps, (unsigned long long)k);
-                            const double ad = (double)absd;
-                            if (ad > 0.0) {
-                                atomicAdd(c0 + kWAbs, weight_units(ad));
-                                atomicAdd(c0 + kWAbs2, weight_units(ad * ad));
-                            }
-                            if (term == kTrans || term == kRDiff) {
-                                const double w = (double)wgt;
-                                atomicAdd(c0 + (term == kTrans ? kWTrans : kWRDiff), weight_units(w));
-                                atomicAdd(c0 + (term == kTrans ? kWTrans2 : kWRDiff2), weight_units(w * w));
-                            } else if (term == kWRoulette) {
-                                atomicAdd(c0 + kWRoulette, 1ull);
-                            } else if (term == kCap) {
-                                atomicAdd(c0 + kWCap, 1ull);
-                            }
-                        } else {
-                            atomicAdd(c0 + kSteps, (unsigned long long)k);
-                            atomicAdd(c0 + term, 1ull);
-                        }
-                    }
-                    if (ballot64(alive) == 0ull) break;
-                }
-                wave_sync_lds();
-                continue;
-            }
-        }
 
         for (int it = 0; it < kStepsPerCheck; ++it) {
             const bool go = alive && k < max_steps;
             int term = (alive && !go) ? (int)kCap : -1;        // step budget used up
             if (go) {
                 ++k;
-                FOS_WALK_STEP(philox4x32_10(p_lo, p_hi, k, item, k0, k1));
+                FOS_WALK_STEP(philox4x32_10(p_lo, p_hi, k, item, k0, k1), tab + slot * rf);
             }
             // ---- tallies of photons that finished in this step ----
             const uint64_t tm = ballot64(term >= 0);
@@ -559,13 +592,231 @@ __device__ __forceinline__ void walk_body(WalkArgs a)
         }
     }
 
-    // exit: flush every slot of this wave
+    // exit (or, in the tail build, the start of the drain phase): flush
+    // every slot of this wave
     wave_sync_lds();
     for (int sl = 0; sl < kSlots; ++sl) {
         const int it = slot_item[sl];
         if (it >= 0 && lane < NT) {
             const unsigned long long v = cnt[sl * NT + lane];
             if (v) atomicAdd(a.tallies + (size_t)it * NT + lane, v);
+        }
+    }
+
+    if constexpr (TAIL) {
+        // ---------------- drain: nothing left to claim ----------------
+        // The slots are flushed: from here on a lane reads its item's record
+        // from the item table and a finishing photon adds to its item's
+        // tallies in HBM, so photons can move between waves.
+        //
+        // Regrouping (regroup_lanes > 0).  A wave left with at most
+        // regroup_lanes photons writes their whole state (item, photon,
+        // step, depth, direction, remaining free path, layer, and the
+        // packet's weights) to the hand-off list and leaves, freeing its
+        // slot on the SIMD; waves with idle lanes take listed photons over.
+        // A photon's draws depend only on (photon, step, item, seed), so it
+        // continues with the same draws and decisions wherever it runs: the
+        // tallies are the same bits.  A wave hands off at most once, and
+        // only while more than regroup_min_waves waves are alive and the
+        // list holds fewer than 64 untaken photons, so the list stays
+        // within hand_cap = waves x regroup_lanes and is taken up promptly.
+        // Every wave leaves through wave_leave(): the wave whose leaving
+        // takes the count of live waves to zero takes whatever is still
+        // listed, so no photon is left behind.
+        //
+        // Tail phase (tail_lanes > 0): a wave with at most tail_lanes
+        // photons in flight lets its idle lanes compute their next draws.
+        // With nl photons in flight each gets B = 64 / 2^ceil(log2 nl)
+        // consecutive Philox blocks, one per lane, in the wave's LDS buffer,
+        // and its lane reads the block of each step there instead of running
+        // the ten dependent rounds.  The draws are the same bits.
+        constexpr int RW = WEIGHTED ? 3 : 2;   // float4 per hand-off record
+        const uint4 hv = *harg;
+        unsigned char* const hbase =
+            reinterpret_cast<unsigned char*>(uniform_u64(((uint64_t)hv.y << 32) | (uint64_t)hv.x));
+        const uint32_t hand_cap = (uint32_t)__builtin_amdgcn_readfirstlane((int)hv.z);
+        const uint32_t hw = (uint32_t)__builtin_amdgcn_readfirstlane((int)hv.w);
+        const bool regroup = (hw & 0xFFu) != 0u;
+        unsigned long long* const ctl = reinterpret_cast<unsigned long long*>(hbase);
+        // wstate: bits 0-7, drain rounds before the next look at an empty
+        // list (doubling from kAbsorbEvery up to kAbsorbMax while it stays
+        // empty); bits 8-15, the current wait; bits 16-23, rounds before the
+        // next hand-off attempt; kHanded: this wave has handed off (never
+        // twice) or found the live-wave count at or below the floor (it only
+        // falls) -- either way it does not try again.
+        constexpr int kHanded = 1 << 24;
+        int wstate = 0;
+        for (;;) {
+            uint64_t dead = ballot64(!alive);
+            // ---- take over listed photons into idle lanes ----
+            if (regroup && dead != 0ull && (dead == ~0ull || __popcll(dead) >= a.refill_min)) {
+                if ((wstate & 0xFF) > 0 && dead != ~0ull) {
+                    --wstate;
+                } else {
+                    int take = 0;
+                    unsigned long long hb = 0ull;
+                    if (lane == 0) {
+                        unsigned long long h = hand_load(ctl + kHandClaimed);
+                        for (int t = 0; t < 4; ++t) {
+                            const unsigned long long r = hand_load(ctl + kHandReserved);
+                            if (r <= h) break;
+                            const unsigned long long want = (unsigned long long)__popcll(dead);
+                            const unsigned long long n = r - h < want ? r - h : want;
+                            if (__hip_atomic_compare_exchange_strong(ctl + kHandClaimed, &h, h + n, __ATOMIC_RELAXED,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                                take = (int)n;
+                                hb = h;
+                                break;
+                            }
+                        }
+                    }
+                    take = __builtin_amdgcn_readfirstlane(take);
+                    hb = uniform_u64(hb);
+                    if (take == 0) {
+                        // list empty: wait twice as long as last time
+                        int w = (wstate >> 8) & 0xFF;
+                        w = w == 0 ? kAbsorbEvery : (2 * w > kAbsorbMax ? kAbsorbMax : 2 * w);
+                        wstate = (wstate & ~0xFFFF) | (w << 8) | w;
+                    } else {
+                        wstate &= ~0xFFFF;
+                        const int rank = lane_rank(dead);
+                        const bool mine = !alive && rank < take;
+                        const unsigned long long j = hb + (unsigned long long)rank;
+                        // each record's writer sets its flag right after reserving it
+                        bool ready = !mine;
+                        for (int sp = 0; sp < kHandSpins; ++sp) {
+                            if (!ready)
+                                ready = __hip_atomic_load(
+                                            reinterpret_cast<unsigned int*>(hbase + hand_flags_offset()) + j,
+                                            __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+                            if (ballot64(!ready) == 0ull) break;
+                            __builtin_amdgcn_s_sleep(2);
+                        }
+                        if (mine) {
+                            if (ready) {
+                                const float4* hr =
+                                    reinterpret_cast<const float4*>(hbase + hand_records_offset(hand_cap)) + j * RW;
+                                const float4 r0 = hr[0], r1 = hr[1];
+                                item = __float_as_uint(r0.x);
+                                p_lo = __float_as_uint(r0.y);
+                                p_hi = __float_as_uint(r0.z);
+                                k = __float_as_uint(r0.w);
+                                z = r1.x;
+                                uz = r1.y;
+                                s = r1.z;
+                                layer = __float_as_int(r1.w);
+                                if constexpr (WEIGHTED) {
+                                    const float4 r2 = hr[2];
+                                    wgt = r2.x;
+                                    absd = r2.y;
+                                }
+                                load_layer(a.table + (size_t)item * rf, layer, P);
+                                alive = true;
+                            } else {
+                                atomicAdd(ctl + kHandLost, 1ull);
+                            }
+                        }
+                        dead = ballot64(!alive);
+                    }
+                }
+            }
+            if (dead == ~0ull) {           // nothing in flight
+                if (!regroup || wave_leave(ctl, lane)) break;
+                continue;
+            }
+            const int nl = 64 - __popcll(dead);
+            // ---- hand the few photons in flight to other waves and leave ----
+            if (regroup && !(wstate & kHanded) && (uint32_t)nl <= (hw & 0xFFu) && (wstate & 0xFF0000) == 0) {
+                // give: 1 handed off, 0 try again later, -1 never (too few waves alive)
+                int give = 0;
+                unsigned long long gb = 0ull;
+                if (lane == 0) {
+                    const unsigned long long aw = hand_load(ctl + kHandWaves);
+                    if (aw <= (unsigned long long)(hw >> 8)) {
+                        give = -1;
+                    } else {
+                        unsigned long long r = hand_load(ctl + kHandReserved);
+                        const unsigned long long h = hand_load(ctl + kHandClaimed);
+                        if (r - h < 64ull && r + (unsigned long long)nl <= (unsigned long long)hand_cap &&
+                            __hip_atomic_compare_exchange_strong(ctl + kHandReserved, &r, r + (unsigned long long)nl,
+                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+                            give = 1;
+                            gb = r;
+                        }
+                    }
+                }
+                give = __builtin_amdgcn_readfirstlane(give);
+                if (give < 0) wstate |= kHanded;
+                if (give == 0) wstate |= kHandRetry << 16;
+                if (give > 0) {
+                    gb = uniform_u64(gb);
+                    if (alive) {
+                        const unsigned long long j = gb + (unsigned long long)lane_rank(~dead);
+                        float4* hr = reinterpret_cast<float4*>(hbase + hand_records_offset(hand_cap)) + j * RW;
+                        hr[0] = make_float4(__uint_as_float(item), __uint_as_float(p_lo), __uint_as_float(p_hi),
+                                            __uint_as_float(k));
+                        hr[1] = make_float4(z, uz, s, __int_as_float(layer));
+                        if constexpr (WEIGHTED) hr[2] = make_float4(wgt, absd, 0.f, 0.f);
+                        __hip_atomic_store(reinterpret_cast<unsigned int*>(hbase + hand_flags_offset()) + j, 1u,
+                                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        alive = false;
+                    }
+                    wstate |= kHanded;
+                    if (wave_leave(ctl, lane)) break;
+                    continue;
+                }
+            } else if ((wstate & 0xFF0000) != 0) {
+                wstate -= 1 << 16;
+            }
+            if (nl <= a.tail_lanes) {
+                // ---- tail phase: steps on prepared draws ----
+                const uint64_t live = ballot64(alive && k < max_steps);
+                const int nlive = __popcll(live);
+                int lg = 0;
+                while ((1 << lg) < nlive) ++lg;
+                const int B = 64 >> lg;
+                {
+                    // this lane prepares draw o of the q-th photon in flight
+                    const int q = lane >> (6 - lg);
+                    const int o = lane & (B - 1);
+                    uint64_t m = live;
+                    for (int t = 0; t < q && m; ++t) m &= m - 1;
+                    const int src = m ? (int)__builtin_ctzll(m) : 0;
+                    const uint32_t sp_lo = __shfl(p_lo, src), sp_hi = __shfl(p_hi, src);
+                    const uint32_t s_k = __shfl(k, src), s_item = __shfl(item, src);
+                    drw[lane] = philox4x32_10(sp_lo, sp_hi, s_k + 1u + (uint32_t)o, s_item, k0, k1);
+                }
+                wave_sync_lds();
+                const int base = (alive && k < max_steps) ? (lane_rank(live) << (6 - lg)) : 0;
+                for (int j = 0; j < B; ++j) {
+                    const bool go = alive && k < max_steps;
+                    int term = (alive && !go) ? (int)kCap : -1;
+                    if (go) {
+                        ++k;
+                        FOS_WALK_STEP(drw[base + j], a.table + (size_t)item * rf);
+                    }
+                    if (term >= 0) {
+                        alive = false;
+                        finish_photon<WEIGHTED>(a.tallies + (size_t)item * NT, term, k, wgt, absd);
+                    }
+                    if (ballot64(alive) == 0ull) break;
+                }
+                wave_sync_lds();
+                continue;
+            }
+            for (int it = 0; it < kStepsPerCheck; ++it) {
+                const bool go = alive && k < max_steps;
+                int term = (alive && !go) ? (int)kCap : -1;
+                if (go) {
+                    ++k;
+                    FOS_WALK_STEP(philox4x32_10(p_lo, p_hi, k, item, k0, k1), a.table + (size_t)item * rf);
+                }
+                if (term >= 0) {
+                    alive = false;
+                    finish_photon<WEIGHTED>(a.tallies + (size_t)item * NT, term, k, wgt, absd);
+                }
+            }
         }
     }
 }
@@ -576,8 +827,12 @@ __global__ void walk(WalkArgs a)
     walk_body<kStepsPerCheck, WEIGHTED, SINGLE, false>(a);
 }
 
+// The drain phase lifts the tail build's scalar registers just past what 8
+// waves per SIMD allow (103 of 102 for the analog one-layer build); capped at
+// 102, the allocator spills one scalar (the LDS address of the drain's
+// buffers) to a vector lane outside both loops and the build keeps 8 waves.
 template <int kStepsPerCheck, bool WEIGHTED, bool SINGLE>
-__global__ void walk_long(WalkArgs a)
+__global__ __attribute__((amdgpu_num_sgpr(102))) void walk_long(WalkArgs a)
 {
     walk_body<kStepsPerCheck, WEIGHTED, SINGLE, true>(a);
 }
@@ -588,12 +843,22 @@ size_t walk_lds_bytes(int block_size, int max_layers, bool weighted, bool tail)
     const int nt = weighted ? kNTallyW : kNTally;
     return (size_t)nw * kSlots * rec_f4(max_layers) * sizeof(float4) +
            (size_t)nw * kSlots * nt * sizeof(unsigned long long) + (size_t)nw * kSlots * sizeof(int) +
-           (tail ? (size_t)nw * 64 * sizeof(uint4) : 0);
+           (tail ? (size_t)nw * 65 * sizeof(uint4) : 0);
+}
+
+hipError_t launch_reset_handoff(const WalkArgs& a, hipStream_t st)
+{
+    if (a.regroup_lanes <= 0) return hipSuccess;
+    uint64_t blocks = ((uint64_t)a.hand_cap + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(reset_handoff, dim3((unsigned)blocks), dim3(256), 0, st, a.hand, (uint64_t)a.hand_cap);
+    return hipGetLastError();
 }
 
 hipError_t launch_walk(const WalkArgs& a, int grid, int block, hipStream_t st, bool weighted)
 {
-    const bool tail = a.tail_lanes > 0;
+    const bool tail = a.tail_lanes > 0 || a.regroup_lanes > 0;
     const size_t lds = walk_lds_bytes(block, a.max_layers, weighted, tail);
     const bool single = a.max_layers == 1;
     if (tail) {

@@ -59,7 +59,8 @@ fos_status check_launch(fos_ctx* c, const fos_mc_launch& L)
         return fail(c, FOS_E_INVALID_ARG, "launch.max_steps must be in [1, 2^32-1]");
     if (L.tail_lanes < -1 || L.tail_lanes > 64)
         return fail(c, FOS_E_INVALID_ARG, "launch.tail_lanes must be in [-1, 64]");
-    if (L.reserved != 0) return fail(c, FOS_E_INVALID_ARG, "launch.reserved must be 0");
+    if (L.regroup_lanes < -1 || L.regroup_lanes > 32)
+        return fail(c, FOS_E_INVALID_ARG, "launch.regroup_lanes must be in [-1, 32]");
     return FOS_OK;
 }
 
@@ -96,7 +97,7 @@ fos_mc_launch merge(const fos_mc_launch& d, const fos_mc_launch* o)
     if (o->blocks_per_cu) r.blocks_per_cu = o->blocks_per_cu;
     if (o->max_steps) r.max_steps = o->max_steps;
     if (o->tail_lanes) r.tail_lanes = o->tail_lanes;
-    if (o->reserved) r.reserved = o->reserved;
+    if (o->regroup_lanes) r.regroup_lanes = o->regroup_lanes;
     return r;
 }
 
@@ -252,6 +253,7 @@ fos_status fos_create(int hip_device, fos_ctx** out)
     c->defaults.blocks_per_cu = 8;
     c->defaults.max_steps = 100000000ull;
     c->defaults.tail_lanes = -1;
+    c->defaults.regroup_lanes = -1;
     DeviceGuard g(hip_device);
     if (hipMalloc(reinterpret_cast<void**>(&c->chunk_counter), 256) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->err_dev), 256) != hipSuccess ||
@@ -292,6 +294,7 @@ void fos_destroy(fos_ctx* c)
         if (c->tune_table) (void)hipFree(c->tune_table);
         if (c->tune_prefix) (void)hipFree(c->tune_prefix);
         if (c->tune_buf) (void)hipFree(c->tune_buf);
+        if (c->hand_buf) (void)hipFree(c->hand_buf);
         if (c->seed_dev) (void)hipFree(c->seed_dev);
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -384,6 +387,39 @@ static hipError_t enqueue_queue_reset(fos_ctx* c, unsigned long long* tal, int c
     return fos::launch_chunk_scan(c->table, fos::rec_f4(c->max_layers), c->n_items, chunk, cap, c->chunk_prefix, st);
 }
 
+// Waves of a launch, and records its hand-off list needs (0 without regrouping).
+static uint64_t hand_records(const fos_ctx* c, const fos_mc_launch& L)
+{
+    if (L.regroup_lanes <= 0) return 0;
+    return (uint64_t)c->n_cu * (uint64_t)L.blocks_per_cu * (uint64_t)(L.block_size / 64) * (uint64_t)L.regroup_lanes;
+}
+
+// Grow the context's hand-off list to what launch L needs (before any
+// capture: allocation happens here, never in the enqueued work).
+static hipError_t ensure_hand(fos_ctx* c, const fos_mc_launch& L, bool weighted)
+{
+    const uint64_t cap = hand_records(c, L);
+    if (cap == 0) return hipSuccess;
+    return grow(c->hand_buf, c->hand_buf_bytes, fos::hand_bytes(cap, weighted));
+}
+
+fos_status fos_mc_handoff_counts(fos_ctx* c, uint64_t* handed, uint64_t* lost, void* hip_stream)
+{
+    if (!c) return FOS_E_INVALID_ARG;
+    c->err.clear();
+    unsigned long long w[4] = {0, 0, 0, 0};
+    if (c->hand_buf) {
+        DeviceGuard g(c->device);
+        hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+        hipError_t e = hipMemcpyAsync(w, c->hand_buf, sizeof w, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hand-off counters");
+    }
+    if (handed) *handed = w[0];
+    if (lost) *lost = w[3];
+    return FOS_OK;
+}
+
 static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed, unsigned long long* tal)
 {
     fos::WalkArgs a{};
@@ -401,6 +437,10 @@ static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed
     a.chunk = L.chunk;
     a.refill_min = L.refill_min;
     a.tail_lanes = L.tail_lanes < 0 ? 0 : L.tail_lanes;
+    a.regroup_lanes = L.regroup_lanes < 0 ? 0 : L.regroup_lanes;
+    a.regroup_min_waves = 4 * c->n_cu;        // one wave per SIMD
+    a.hand = c->hand_buf;
+    a.hand_cap = (uint32_t)hand_records(c, L);
     return a;
 }
 
@@ -420,9 +460,12 @@ static fos_status execute(fos_ctx* c, uint64_t seed, const fos_mc_launch* launch
     DeviceGuard g(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
-    hipError_t e = enqueue_queue_reset(c, tal, L.chunk, 0, st, weighted ? fos::kNTallyW : fos::kNTally);
+    hipError_t e = ensure_hand(c, L, weighted);
+    if (e != hipSuccess) return hip_fail(c, e, "hand-off list");
+    e = enqueue_queue_reset(c, tal, L.chunk, 0, st, weighted ? fos::kNTallyW : fos::kNTally);
     if (e != hipSuccess) return hip_fail(c, e, "reset kernels");
     const fos::WalkArgs a = walk_args(c, L, seed, tal);
+    if ((e = fos::launch_reset_handoff(a, st)) != hipSuccess) return hip_fail(c, e, "reset kernels");
     const int grid = c->n_cu * L.blocks_per_cu;
     if ((e = fos::launch_walk(a, grid, L.block_size, st, weighted)) != hipSuccess)
         return hip_fail(c, e, "walk kernel");
@@ -582,6 +625,8 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t sample_photons, f
     if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
         return fail(c, FOS_E_DEVICE, "event creation failed");
     auto time_one = [&](const fos_mc_launch& L, float& ms) -> hipError_t {
+        hipError_t r0 = ensure_hand(c, L, false);
+        if (r0 != hipSuccess) return r0;
         fos::WalkArgs a = walk_args(c, L, seed, c->tune_tallies);
         a.table = c->tune_table;
         a.n_items = m;
@@ -591,7 +636,8 @@ fos_status fos_mc_autotune(fos_ctx* c, uint64_t seed, uint64_t sample_photons, f
         for (int rep = 0; rep < 3; ++rep) {
             hipError_t r;
             if ((r = fos::launch_reset(c->tune_tallies, c->chunk_counter, m, fos::kNTally, st)) != hipSuccess ||
-                (r = fos::launch_chunk_scan(c->tune_table, rf, m, L.chunk, 0, c->tune_prefix, st)) != hipSuccess)
+                (r = fos::launch_chunk_scan(c->tune_table, rf, m, L.chunk, 0, c->tune_prefix, st)) != hipSuccess ||
+                (r = fos::launch_reset_handoff(a, st)) != hipSuccess)
                 return r;
             if ((r = hipEventRecord(ev0, st)) != hipSuccess) return r;
             if ((r = fos::launch_walk(a, grid, L.block_size, st)) != hipSuccess) return r;
@@ -662,6 +708,8 @@ fos_status fos_mc_graph_capture(fos_ctx* c, const fos_mc_launch* launch, uint64_
         return hip_fail(c, e, "capture stream");
     if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
     if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if ((e = ensure_hand(c, L, false)) != hipSuccess) return hip_fail(c, e, "hand-off list");
+    c->graph_hand = L.regroup_lanes > 0 ? c->hand_buf : nullptr;
     // order the capture after the caller's work (the prepared table)
     if ((e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(hip_stream))) != hipSuccess)
         return hip_fail(c, e, "graph capture");
@@ -673,6 +721,7 @@ fos_status fos_mc_graph_capture(fos_ctx* c, const fos_mc_launch* launch, uint64_
         fos::WalkArgs a = walk_args(c, L, 0, tal);
         a.seed_ptr = reinterpret_cast<const uint64_t*>(c->seed_dev);
         e1 = enqueue_queue_reset(c, tal, L.chunk, 0, c->capture_stream);
+        if (e1 == hipSuccess) e1 = fos::launch_reset_handoff(a, c->capture_stream);
         if (e1 == hipSuccess) e1 = fos::launch_walk(a, c->n_cu * L.blocks_per_cu, L.block_size, c->capture_stream);
     }
     e = hipStreamEndCapture(c->capture_stream, &c->graph);
@@ -691,6 +740,8 @@ fos_status fos_mc_graph_launch(fos_ctx* c, uint64_t seed, void* hip_stream)
     if (!c->graph_exec) return fail(c, FOS_E_NOT_PREPARED, "no captured graph (call fos_mc_graph_capture)");
     if (c->graph_epoch != c->prepare_epoch)
         return fail(c, FOS_E_NOT_PREPARED, "problem re-prepared since the graph was captured");
+    if (c->graph_hand && c->graph_hand != c->hand_buf)
+        return fail(c, FOS_E_NOT_PREPARED, "hand-off list reallocated since the graph was captured (capture again)");
     DeviceGuard g(c->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e = fos::launch_fill_u64(c->seed_dev, (unsigned long long)seed, 1, st);
@@ -787,6 +838,9 @@ fos_status fos_mc_run_noalloc(fos_ctx* c, const fos_mc_problem* p, uint64_t seed
         L.chunk = auto_chunk_for(c->n_cu, p->n_items, (uint64_t)c->aux_host[3], L);
     fos_status s = check_launch(c, L);
     if (s != FOS_OK) return s;
+    if (L.regroup_lanes > 0)
+        return fail(c, FOS_E_INVALID_ARG, "launch.regroup_lanes: regrouping needs the context's hand-off list, "
+                                          "which the allocation-free walk does not use");
     // queue and walk, as fos_mc_execute does, on the scratch buffers
     unsigned long long* tal = reinterpret_cast<unsigned long long*>(tallies);
     if ((e = fos::launch_reset(tal, words + 2, p->n_items, fos::kNTally, st)) != hipSuccess ||

@@ -63,10 +63,10 @@ class fos_train_opts(Structure):
 class fos_mc_launch(Structure):
     _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
                 ("blocks_per_cu", c_int32), ("max_steps", c_uint64), ("tail_lanes", c_int32),
-                ("reserved", c_int32)]
+                ("regroup_lanes", c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -116,6 +116,8 @@ def lib():
         L.fos_mc_autotune_cache.restype = c_int
         L.fos_mc_graph_capture.argtypes = [c_void_p, POINTER(fos_mc_launch), c_void_p, c_void_p]
         L.fos_mc_graph_capture.restype = c_int
+        L.fos_mc_handoff_counts.argtypes = [c_void_p, POINTER(c_uint64), POINTER(c_uint64), c_void_p]
+        L.fos_mc_handoff_counts.restype = c_int
         L.fos_mc_graph_launch.argtypes = [c_void_p, c_uint64, c_void_p]
         L.fos_mc_graph_launch.restype = c_int
         L.fos_sur_features.argtypes = [c_void_p, POINTER(fos_mc_problem), c_void_p, c_void_p, c_void_p]
@@ -333,6 +335,13 @@ def fos_mc_graph_capture(ctx, tallies, launch=None, stream=None) -> None:
     n = fos_mc_prepared_items(ctx)
     _check(ctx, lib().fos_mc_graph_capture(ctx, _launch(launch), _ptr(tallies, None, n * N_TALLY),
                                            _stream(stream)))
+
+
+def fos_mc_handoff_counts(ctx, stream=None):
+    """(photons handed between waves, hand-offs lost) of the last regrouping walk."""
+    handed, lost = c_uint64(0), c_uint64(0)
+    _check(ctx, lib().fos_mc_handoff_counts(ctx, ctypes.byref(handed), ctypes.byref(lost), _stream(stream)))
+    return int(handed.value), int(lost.value)
 
 
 def fos_mc_graph_launch(ctx, seed: int, stream=None) -> None:

@@ -158,7 +158,7 @@ MAX_CAPPED_FRACTION = 1e-3
 
 
 def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True,
-                      launch=None, launch_sizes=None, launches=None, y=None, on_launch=None):
+                      launch=None, launch_sizes=None, launches=None, y=None, on_launch=None, in_flight: int = 2):
     """n single-layer items labelled by the walk at `photons` each.
     Returns (x [n*8], y [n*3], photon-steps, seconds).  With label=False only
     the features are made (y is None): the items are a function of
@@ -166,10 +166,10 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
 
     The items are ordered by _walk_cost, longest first, and walked in the
     launches of `launch_sizes` (default label_launch_sizes(n)), launch c
-    under seed + c.  Two
-    contexts take turns, each launch on its own stream, so a launch starts
-    on the CUs that the one before it frees while its last long walks run;
-    a launch waits only for the one two back.  Labels depend on (n, seed,
+    under seed + c.  `in_flight` contexts take turns, each launch on its own
+    stream, so a launch starts on the CUs that the ones before it free while
+    their last long walks run; a launch waits only for the one `in_flight`
+    back.  Labels depend on (n, seed,
     chunk) and on that order and those sizes.  A label whose item had more
     than MAX_CAPPED_FRACTION of its photons stopped by the step cap raises.
 
@@ -196,9 +196,11 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
     if y is None:
         y = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    ctx2 = fos.Context(0)
-    ctxs = (ctx, ctx2.handle)
-    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    if in_flight < 1:
+        raise ValueError("in_flight must be >= 1")
+    extra = [fos.Context(0) for _ in range(in_flight - 1)]
+    ctxs = (ctx, *[e.handle for e in extra])
+    streams = [torch.cuda.Stream() for _ in range(in_flight)]
     totals = {"steps": 0, "capped": 0, "worst_capped": 0.0}
     pending = []
 
@@ -208,7 +210,7 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
         m = len(idx)
         t = tal.view(m, fos.N_TALLY)
         rat = torch.zeros(m * 3, dtype=torch.float32, device="cuda")
-        fos.fos_mc_fractions(ctxs[c % 2], tal, rat)
+        fos.fos_mc_fractions(ctxs[c % in_flight], tal, rat)
         y.view(n, 3)[torch.from_numpy(idx).cuda()] = rat.view(m, 3)
         steps, capped = int(t[:, 5].sum().item()), int(t[:, 4].sum().item())
         worst = float((t[:, 4].double() / photons).max().item())
@@ -231,15 +233,15 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
         todo = range(len(sizes)) if launches is None else launches
         starts = np.concatenate([[0], np.cumsum(sizes)])
         for c in todo:
-            if len(pending) == 2:
+            if len(pending) == in_flight:
                 finish(pending.pop(0))
             m = sizes[c]
             idx = order[starts[c]:starts[c] + m]
-            st = streams[c % 2]
+            st = streams[c % in_flight]
             with torch.cuda.stream(st):
                 prob = device_problem({k: v[idx] for k, v in items.items()})
                 tal = torch.zeros(m * fos.N_TALLY, dtype=torch.int64, device="cuda")
-                fos.fos_mc_run(ctxs[c % 2], prob, seed + c, tal, launch=launch, stream=st)
+                fos.fos_mc_run(ctxs[c % in_flight], prob, seed + c, tal, launch=launch, stream=st)
                 done = torch.cuda.Event()
                 done.record(st)
             pending.append((c, idx, tal, done, prob))
@@ -249,7 +251,8 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
             finish(pending.pop(0))
     finally:
         torch.cuda.synchronize()
-        ctx2.close()
+        for e in extra:
+            e.close()
     return x, y, totals["steps"], time.perf_counter() - t0
 
 

@@ -391,6 +391,100 @@ def test_tail_draws_prepared_across_lanes_are_bit_identical(ctx, torch, layers, 
     assert capped.sum() > 0 and (steps / a["photons"]).max() > 1e3
 
 
+def _heavy_tail_bulk(layers):
+    """The heavy-tailed items with 30 times the photons (2.3e6), so that
+    every wave of the default grid is busy when the queue runs out."""
+    a = dict(_heavy_tail_problem(layers))
+    a["photons"] = a["photons"] * 30
+    return a
+
+
+@pytest.mark.parametrize("layers", [1, 2])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_regrouped_drain_is_bit_identical(ctx, torch, layers, weighted):
+    """Waves left with few photons once the queue is empty hand them to
+    other waves through the hand-off list (regroup_lanes), with and without
+    prepared draws and on other grids: every photon continues with the same
+    draws, so the tallies are the same bits as the plain walk's, capped
+    photons included.  Photons were handed off, and none was lost."""
+    from paper_2409_00165_amd import fos
+    from gpu_helpers import device_problem
+    a = _heavy_tail_bulk(layers)
+    prob = device_problem(a)
+    nt = fos.N_TALLY_W if weighted else fos.N_TALLY
+    run = fos.fos_mc_run_weighted if weighted else fos.fos_mc_run
+    base = {"max_steps": 50_000, "chunk": 64}
+    configs = [{"tail_lanes": -1, "regroup_lanes": -1}, {"tail_lanes": -1, "regroup_lanes": 4},
+               {"tail_lanes": -1, "regroup_lanes": 16}, {"tail_lanes": 16, "regroup_lanes": 16},
+               {"tail_lanes": 16, "regroup_lanes": 32, "blocks_per_cu": 16},
+               {"tail_lanes": 8, "regroup_lanes": 8, "block_size": 128}]
+    outs, handed = [], []
+    for cfg in configs:
+        print("regroup case", layers, weighted, cfg, flush=True)
+        tal = torch.full((prob.n_items * nt,), -1, dtype=torch.int64, device="cuda")
+        run(ctx, prob, 4242, tal, launch={**base, **cfg})
+        torch.cuda.synchronize()
+        outs.append(tal.cpu().numpy().reshape(prob.n_items, nt))
+        h, lost = fos.fos_mc_handoff_counts(ctx)
+        assert lost == 0, cfg
+        handed.append(h if cfg["regroup_lanes"] > 0 else 0)
+    print("photons handed off per config", handed, flush=True)
+    for o, cfg in zip(outs[1:], configs[1:]):
+        assert (o == outs[0]).all(), cfg
+    assert min(handed[1:]) > 0
+    t = outs[0]
+    if not weighted:
+        assert (t[:, :5].sum(1) == a["photons"]).all()
+    assert (t[:, 8] if weighted else t[:, 4]).sum() > 0
+
+
+def test_regrouped_walk_full_size_bit_identical(ctx, torch):
+    """The benchmark slab (500 wavelengths x 1e6 photons) in the tail build
+    with regrouping gives the plain walk's tallies bit for bit."""
+    from paper_2409_00165_amd import fos
+    G = load_golden("two_species_500")
+    a = arrays_from_problem(G["problem"])
+    plain = run_gpu(ctx, a, 91)
+    grouped = run_gpu(ctx, a, 91, launch={"tail_lanes": 16, "regroup_lanes": 16})
+    h, lost = fos.fos_mc_handoff_counts(ctx)
+    print("photons handed off", h, flush=True)
+    assert lost == 0 and h > 0
+    assert np.array_equal(plain, grouped)
+
+
+def test_regrouped_graph_replays_match_eager(ctx, torch):
+    """A captured regrouping walk (its hand-off list reset by a kernel inside
+    the graph) replays to the eager tallies, with eager work between."""
+    from paper_2409_00165_amd import fos
+    from gpu_helpers import device_problem
+    a = _heavy_tail_bulk(1)
+    prob = device_problem(a)
+    I = prob.n_items
+    L = {"tail_lanes": 16, "regroup_lanes": 16, "max_steps": 50_000, "chunk": 64}
+    eager = torch.zeros(I * 6, dtype=torch.int64, device="cuda")
+    fos.fos_mc_run(ctx, prob, 5, eager, launch=L)
+    torch.cuda.synchronize()
+    ref = eager.cpu().numpy()
+    out = torch.zeros(I * 6, dtype=torch.int64, device="cuda")
+    fos.fos_mc_graph_capture(ctx, out, launch=L)
+    for rep in range(3):
+        out.fill_(-5)
+        junk = torch.randn(1000, device="cuda").sum()
+        fos.fos_mc_graph_launch(ctx, 5)
+        torch.cuda.synchronize()
+        assert (out.cpu().numpy() == ref).all(), rep
+        assert fos.fos_mc_handoff_counts(ctx)[1] == 0
+        del junk
+
+
+def test_regroup_lanes_are_validated(ctx, torch):
+    from paper_2409_00165_amd import fos
+    a = _det_problem()
+    for bad in (-2, 33):
+        with pytest.raises(fos.FosError, match="regroup_lanes"):
+            run_gpu(ctx, a, 1, launch={"regroup_lanes": bad})
+
+
 def test_per_problem_chunk_keeps_results(torch):
     """A fresh context sizes the claim chunk per problem when no chunk is
     given (small batches get smaller chunks); an explicit launch chunk and a

@@ -87,3 +87,17 @@ def test_noalloc_validates_like_prepare(torch):
         assert "item 37" in str(ei.value) and "g" in str(ei.value)
         torch.cuda.synchronize()
         assert bool((tal == -1).all())
+
+
+def test_noalloc_rejects_regrouping(torch):
+    """Regrouping needs the context's hand-off list, so the allocation-free
+    walk refuses it before any work."""
+    from paper_2409_00165_amd import fos
+    a = _problem(300, 1, 3)
+    with fos.Context(0) as c:
+        prob = device_problem(a)
+        tal = torch.full((prob.n_items * fos.N_TALLY,), -7, dtype=torch.int64, device="cuda")
+        with pytest.raises(fos.FosError, match="regroup"):
+            fos.fos_mc_run_noalloc(c.handle, prob, 1, tal, launch={"regroup_lanes": 8})
+        torch.cuda.synchronize()
+        assert bool((tal == -7).all())

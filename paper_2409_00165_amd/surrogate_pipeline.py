@@ -166,10 +166,11 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
 
     The items are ordered by _walk_cost, longest first, and walked in the
     launches of `launch_sizes` (default label_launch_sizes(n)), launch c
-    under seed + c.  `in_flight` contexts take turns, each launch on its own
-    stream, so a launch starts on the CUs that the ones before it free while
-    their last long walks run; a launch waits only for the one `in_flight`
-    back.  Labels depend on (n, seed,
+    under seed + c.  Every launch is prepared and queued up front, on
+    `in_flight` streams: the first launch on a stream of its own, the others
+    taking turns on the rest, so that a launch starts on the CUs that the
+    ones before it free while their last long walks run.  Labels depend on
+    (n, seed,
     chunk) and on that order and those sizes.  A label whose item had more
     than MAX_CAPPED_FRACTION of its photons stopped by the step cap raises.
 
@@ -195,60 +196,79 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
     order = np.argsort(-_walk_cost(items), kind="stable")
     if y is None:
         y = torch.zeros(n * 3, dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
     if in_flight < 1:
         raise ValueError("in_flight must be >= 1")
-    extra = [fos.Context(0) for _ in range(in_flight - 1)]
-    ctxs = (ctx, *[e.handle for e in extra])
-    streams = [torch.cuda.Stream() for _ in range(in_flight)]
+    sizes = list(launch_sizes) if launch_sizes is not None else label_launch_sizes(n)
+    if sum(sizes) != n or min(sizes) < 1:
+        raise ValueError("launch sizes must be positive and add up to n")
+    todo = list(range(len(sizes)) if launches is None else launches)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
     totals = {"steps": 0, "capped": 0, "worst_capped": 0.0}
-    pending = []
-
-    def finish(job):
-        c, idx, tal, done, _prob = job
-        done.synchronize()
-        m = len(idx)
-        t = tal.view(m, fos.N_TALLY)
-        rat = torch.zeros(m * 3, dtype=torch.float32, device="cuda")
-        fos.fos_mc_fractions(ctxs[c % in_flight], tal, rat)
-        y.view(n, 3)[torch.from_numpy(idx).cuda()] = rat.view(m, 3)
-        steps, capped = int(t[:, 5].sum().item()), int(t[:, 4].sum().item())
-        worst = float((t[:, 4].double() / photons).max().item())
-        totals["steps"] += steps
-        totals["capped"] += capped
-        totals["worst_capped"] = max(totals["worst_capped"], worst)
-        if log:
-            log(f"training labels: launch {c} ({m} items) done, {steps:.3e} photon-steps, {capped} capped photons "
-                f"(item worst {worst:.1e}), {time.perf_counter() - t0:.1f} s")
-        if worst > MAX_CAPPED_FRACTION:
-            raise RuntimeError(f"labelling launch {c}: an item had {worst:.2e} of its photons stopped by the "
-                               f"step cap (more than {MAX_CAPPED_FRACTION})")
-        if on_launch:
-            on_launch(c, steps, capped)
-
+    extra, jobs = [], []
     try:
-        sizes = list(launch_sizes) if launch_sizes is not None else label_launch_sizes(n)
-        if sum(sizes) != n or min(sizes) < 1:
-            raise ValueError("launch sizes must be positive and add up to n")
-        todo = range(len(sizes)) if launches is None else launches
-        starts = np.concatenate([[0], np.cumsum(sizes)])
-        for c in todo:
-            if len(pending) == in_flight:
-                finish(pending.pop(0))
+        # Everything the walks need goes to the device first, while it is
+        # idle: a copy or small kernel issued while persistent walks fill the
+        # CUs waits for a free wave slot, for tens of seconds at times.  Each
+        # launch has a context of its own, prepared here.
+        for j, c in enumerate(todo):
+            if j == 0:
+                cx = ctx
+            else:
+                extra.append(fos.Context(0))
+                cx = extra[-1].handle
             m = sizes[c]
             idx = order[starts[c]:starts[c] + m]
-            st = streams[c % in_flight]
+            prob = device_problem({k: v[idx] for k, v in items.items()})
+            fos.fos_mc_prepare(cx, prob)
+            jobs.append({"c": c, "ctx": cx, "m": m, "prob": prob, "idx": torch.from_numpy(idx).cuda(),
+                         "tal": torch.zeros(m * fos.N_TALLY, dtype=torch.int64, device="cuda"),
+                         "rat": torch.zeros(m * 3, dtype=torch.float32, device="cuda"),
+                         "stats_host": torch.zeros(3, dtype=torch.float64, pin_memory=True)})
+        torch.cuda.synchronize()
+        # The first launch (the longest walks) has a stream of its own; the
+        # others take turns on the remaining streams, each running its
+        # launches back to back.  Each launch's fractions, its rows of y and
+        # its counts follow its walk on its stream.
+        streams = [torch.cuda.Stream() for _ in range(in_flight)]
+        for j, job in enumerate(jobs):
+            st = streams[0 if j == 0 or in_flight == 1 else 1 + (j - 1) % (in_flight - 1)]
+            m = job["m"]
             with torch.cuda.stream(st):
-                prob = device_problem({k: v[idx] for k, v in items.items()})
-                tal = torch.zeros(m * fos.N_TALLY, dtype=torch.int64, device="cuda")
-                fos.fos_mc_run(ctxs[c % in_flight], prob, seed + c, tal, launch=launch, stream=st)
-                done = torch.cuda.Event()
-                done.record(st)
-            pending.append((c, idx, tal, done, prob))
-            if log:
-                log(f"training labels: launch {c} ({m} items) started")
-        while pending:
-            finish(pending.pop(0))
+                fos.fos_mc_execute(job["ctx"], seed + job["c"], job["tal"], launch=launch, stream=st)
+                job["walked"] = torch.cuda.Event()
+                job["walked"].record(st)
+                fos.fos_mc_fractions(job["ctx"], job["tal"], job["rat"], stream=st)
+                y.view(n, 3)[job["idx"]] = job["rat"].view(m, 3)
+                t = job["tal"].view(m, fos.N_TALLY)
+                stats = torch.stack([t[:, 5].sum().double(), t[:, 4].sum().double(),
+                                     (t[:, 4].double() / photons).max()])
+                job["stats_host"].copy_(stats, non_blocking=True)
+                job["done"] = torch.cuda.Event()
+                job["done"].record(st)
+        if log:
+            log(f"training labels: {len(jobs)} launches queued on {in_flight} streams")
+        # report each launch as it ends, in the order they end
+        left = list(range(len(jobs)))
+        while left:
+            ended = [j for j in left if jobs[j]["done"].query()]
+            for j in ended:
+                job = jobs[j]
+                steps, capped, worst = (float(v) for v in job["stats_host"].tolist())
+                steps, capped = int(steps), int(capped)
+                totals["steps"] += steps
+                totals["capped"] += capped
+                totals["worst_capped"] = max(totals["worst_capped"], worst)
+                if log:
+                    log(f"training labels: launch {job['c']} ({job['m']} items) done, {steps:.3e} photon-steps, "
+                        f"{capped} capped photons (item worst {worst:.1e}), {time.perf_counter() - t0:.1f} s")
+                if worst > MAX_CAPPED_FRACTION:
+                    raise RuntimeError(f"labelling launch {job['c']}: an item had {worst:.2e} of its photons "
+                                       f"stopped by the step cap (more than {MAX_CAPPED_FRACTION})")
+                if on_launch:
+                    on_launch(job["c"], steps, capped)
+            left = [j for j in left if j not in ended]
+            if left and not ended:
+                time.sleep(0.02)
     finally:
         torch.cuda.synchronize()
         for e in extra:

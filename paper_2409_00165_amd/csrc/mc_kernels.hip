@@ -449,7 +449,20 @@ __device__ __forceinline__ void walk_body(WalkArgs a)
             if (src_next >= src_end) {
                 if (queue_done) break;
                 const int ns = (src_slot + 1) % kSlots;
-                if (ballot64(alive && slot == ns) != 0ull) break;   // slot still draining
+                if (ballot64(alive && slot == ns) != 0ull) {   // slot still draining
+                    if constexpr (TAIL) {
+                        // A wave whose oldest slot holds a long walk cannot
+                        // claim, so it would not learn that the queue is
+                        // empty until that walk ends: it looks at the queue
+                        // itself, and enters the drain phase once it is.
+                        int qd = 0;
+                        if (lane == 0)
+                            qd = __hip_atomic_load(a.chunk_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                 a.chunk_prefix[a.n_items];
+                        queue_done = __builtin_amdgcn_readfirstlane(qd) != 0;
+                    }
+                    break;
+                }
                 // claim the next global chunk; lane 0 finds its item by
                 // binary search in the chunk prefix
                 int c_item = -1;

@@ -438,7 +438,7 @@ static fos::WalkArgs walk_args(fos_ctx* c, const fos_mc_launch& L, uint64_t seed
     a.refill_min = L.refill_min;
     a.tail_lanes = L.tail_lanes < 0 ? 0 : L.tail_lanes;
     a.regroup_lanes = L.regroup_lanes < 0 ? 0 : L.regroup_lanes;
-    a.regroup_min_waves = 4 * c->n_cu;        // one wave per SIMD
+    a.regroup_min_waves = c->n_cu;            // one wave per CU
     a.hand = c->hand_buf;
     a.hand_cap = (uint32_t)hand_records(c, L);
     return a;

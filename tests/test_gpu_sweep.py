@@ -177,3 +177,26 @@ def test_training_labels_follow_their_items_across_launches(torch):
     assert (z <= 5.0).all()
     assert np.abs(a - b).mean() < 0.01
     c.close()
+
+
+def test_labels_do_not_depend_on_streams_or_regrouping(torch):
+    """The labelling launches may run on any number of streams, with or
+    without regrouping and prepared draws: each label is its item's walk
+    under its launch's seed, so the labels, photon-steps and features are
+    the same bits."""
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    c = fos.Context(0)
+    h = c.handle
+    n, ph, sizes = 3000, 2000, [500, 500, 800, 1200]
+    runs = []
+    for nf, launch in ((1, {"tail_lanes": -1, "regroup_lanes": -1}), (2, {"tail_lanes": 16}),
+                       (4, {"tail_lanes": 16, "regroup_lanes": 32}), (3, {"tail_lanes": -1, "regroup_lanes": 8})):
+        print("labels with", nf, "streams and launch", launch, flush=True)
+        x, y, steps, _ = SP.make_training_set(h, n, ph, seed=31, chunk=1000, launch_sizes=sizes, launch=launch,
+                                              in_flight=nf)
+        torch.cuda.synchronize()
+        runs.append((x.cpu().numpy(), y.cpu().numpy(), steps))
+    for x, y, steps in runs[1:]:
+        assert np.array_equal(x, runs[0][0]) and np.array_equal(y, runs[0][1]) and steps == runs[0][2]
+    c.close()

@@ -136,7 +136,7 @@ typedef struct {
                                wave with no photons left to claim and at most this
                                many in flight writes their state to a hand-off
                                list in HBM and leaves, and waves with idle lanes
-                               take them over, while more than one wave per SIMD
+                               take them over, while more than one wave per CU
                                is alive; -1: off; 1..32, -1.  Needs a context
                                hand-off list of (CUs x blocks_per_cu x waves per
                                block x regroup_lanes) records of 32 B (48 B

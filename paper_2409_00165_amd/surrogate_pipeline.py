@@ -235,8 +235,6 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
             m = job["m"]
             with torch.cuda.stream(st):
                 fos.fos_mc_execute(job["ctx"], seed + job["c"], job["tal"], launch=launch, stream=st)
-                job["walked"] = torch.cuda.Event()
-                job["walked"].record(st)
                 fos.fos_mc_fractions(job["ctx"], job["tal"], job["rat"], stream=st)
                 y.view(n, 3)[job["idx"]] = job["rat"].view(m, 3)
                 t = job["tal"].view(m, fos.N_TALLY)

@@ -513,7 +513,10 @@ def surrogate_train_main(args):
     ctx = fos.Context(0)
     h = ctx.handle
     say("surrogate training pipeline start")
-    launch = {k: v for k, v in (("tail_lanes", args.tail_lanes), ("regroup_lanes", args.regroup_lanes)) if v} or None
+    launch = {k: v for k, v in (("tail_lanes", args.tail_lanes), ("regroup_lanes", args.regroup_lanes)) if v}
+    if args.launch:
+        launch.update(json.loads(args.launch))
+    launch = launch or None
     n_tr = args.train_samples
     if args.load_data:
         # stored labels, re-joined to features regenerated from the same item seeds
@@ -953,7 +956,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0x5EED)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", type=str, default="", help="JSON fos_mc_launch overrides")
+    ap.add_argument("--launch", type=str, default="",
+                    help="JSON fos_mc_launch overrides (the walk of the default workload; surrogate_train: the label walks)")
     ap.add_argument("--workload", default="two_species_500",
                     choices=["two_species_500", "stacks_3layer", "surrogate", "surrogate_train", "paper_context",
                              "weighted", "optics", "valu_issue", "lone_step"],

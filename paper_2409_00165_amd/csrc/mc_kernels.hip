@@ -4,8 +4,13 @@
 //                   (entry Fresnel reflectance, refracted cosine, per-layer
 //                   extinction, albedo, HG constants, interface ratios).
 //   reset_run     : zero the caller's tallies and the chunk counter.
+//   reset_handoff : clear the hand-off list of a regrouping walk.
 //   chunk_scan    : prefix of per-item chunk counts (the work queue).
 //   walk          : the persistent photon walk (one photon per lane).
+//   walk_long     : the same walk built for heavy-tailed batches: once its
+//                   queue is empty a wave enters a drain phase that can hand
+//                   its last photons to other waves and prepare their draws
+//                   on idle lanes.
 //   philox_words / eval_fresnel / eval_hg : thin kernels exposing the device
 //                   building blocks to the test-suite.
 //

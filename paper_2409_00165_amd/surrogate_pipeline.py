@@ -157,6 +157,15 @@ def label_launch_sizes(n: int, first: int = 1024, largest: int = 262_144):
 MAX_CAPPED_FRACTION = 1e-3
 
 
+def label_stream(j: int, in_flight: int) -> int:
+    """Stream of the j-th labelling launch: the first (the longest walks)
+    has stream 0 to itself, the others take turns on streams 1..in_flight-1
+    (with one stream, everything runs on it)."""
+    if j == 0 or in_flight == 1:
+        return 0
+    return 1 + (j - 1) % (in_flight - 1)
+
+
 def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000, log=None, label: bool = True,
                       launch=None, launch_sizes=None, launches=None, y=None, on_launch=None, in_flight: int = 2):
     """n single-layer items labelled by the walk at `photons` each.
@@ -231,7 +240,7 @@ def make_training_set(ctx, n: int, photons: int, seed: int, chunk: int = 125_000
         # its counts follow its walk on its stream.
         streams = [torch.cuda.Stream() for _ in range(in_flight)]
         for j, job in enumerate(jobs):
-            st = streams[0 if j == 0 or in_flight == 1 else 1 + (j - 1) % (in_flight - 1)]
+            st = streams[label_stream(j, in_flight)]
             m = job["m"]
             with torch.cuda.stream(st):
                 fos.fos_mc_execute(job["ctx"], seed + job["c"], job["tal"], launch=launch, stream=st)

@@ -38,3 +38,12 @@ def test_walk_cost_orders_the_training_recipe_longest_first():
     head = order[: len(order) // 100]
     assert np.median(tau_red[head]) > np.quantile(tau_red, 0.9)
     assert np.all(np.isfinite(c)) and np.all(c >= 0)
+
+
+def test_label_streams_give_the_first_launch_a_stream_of_its_own():
+    from paper_2409_00165_amd import surrogate_pipeline as SP
+    assert [SP.label_stream(j, 1) for j in range(5)] == [0, 0, 0, 0, 0]
+    assert [SP.label_stream(j, 2) for j in range(5)] == [0, 1, 1, 1, 1]
+    got = [SP.label_stream(j, 8) for j in range(22)]
+    assert got[0] == 0 and 0 not in got[1:]
+    assert got[1:8] == [1, 2, 3, 4, 5, 6, 7] and got[8:15] == [1, 2, 3, 4, 5, 6, 7]

@@ -5,7 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 and shares no source with it.
 
 The numerical work is in ``fos_oracle.c`` (plain C99, double precision,
-POSIX threads across items); ``mlp.py`` holds the numpy FP64 surrogate oracle.
+POSIX threads across items); ``mlp.py`` holds the numpy FP64 surrogate oracle
+and ``output.py`` the numpy FP64 output stage (eq. (21), band emittance,
+colour).
 This module only marshals arguments through ctypes.
 
 Parity status (each function's pins live in ``tests/test_oracle_*.py``):

@@ -39,6 +39,17 @@ SOLAR_RANGE_UM = (0.28, 2.5)      # eq. (21) needs the simulated range to cover 
 VISIBLE_RANGE_UM = (0.38, 0.78)   # the colour needs the simulated range to cover this
 PLANCK_C2_UM_K = 14387.769        # second radiation constant hc/k, um K
 
+
+def _f32(v):
+    return np.float32(v)
+
+
+def _covers(lam, lo, hi):
+    """Whether the grid spans [lo, hi].  The grid reaches the device in
+    single precision, so this decision (and band membership below) is taken
+    on single-precision values on both sides."""
+    return len(lam) >= 2 and _f32(lam[0]) <= _f32(lo) and _f32(lam[-1]) >= _f32(hi)
+
 # ---------------------------------------------------------------------------
 # spectra on the grid
 # ---------------------------------------------------------------------------
@@ -82,7 +93,7 @@ def solar_totals(lam, rat, solar):
     lam = np.asarray(lam, np.float64)
     rat = np.asarray(rat, np.float64)
     D = rat.shape[0]
-    if solar is None or len(lam) < 2 or lam[0] > SOLAR_RANGE_UM[0] or lam[-1] < SOLAR_RANGE_UM[1]:
+    if solar is None or not _covers(lam, *SOLAR_RANGE_UM):
         return np.full((D, 3), np.nan)
     G = spectrum_on_grid(solar[0], solar[1], lam)
     den = trapezoid(lam, G)
@@ -95,7 +106,8 @@ def band_emittance(lam, absorptance, lo_um, hi_um, temperature_k):
     NaN when fewer than two grid points fall in the band."""
     lam = np.asarray(lam, np.float64)
     A = np.asarray(absorptance, np.float64)
-    inside = (lam >= lo_um) & (lam <= hi_um)
+    lam32 = lam.astype(np.float32)
+    inside = (lam32 >= _f32(lo_um)) & (lam32 <= _f32(hi_um))
     if temperature_k <= 0 or inside.sum() < 2:
         return np.full(A.shape[0], np.nan)
     sub = lam[inside]
@@ -136,7 +148,7 @@ def tristimulus(lam, reflectance, illuminant=None):
     lam = np.asarray(lam, np.float64)
     R = np.asarray(reflectance, np.float64)
     D = R.shape[0]
-    if len(lam) < 2 or lam[0] > VISIBLE_RANGE_UM[0] or lam[-1] < VISIBLE_RANGE_UM[1]:
+    if not _covers(lam, *VISIBLE_RANGE_UM):
         return np.full((D, 3), np.nan), np.full(3, np.nan)
     S = np.ones_like(lam) if illuminant is None else spectrum_on_grid(illuminant[0], illuminant[1], lam)
     cmf = cmf_cie1931(lam)

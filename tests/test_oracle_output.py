@@ -66,6 +66,9 @@ def test_solar_totals_need_the_solar_range_and_a_spectrum():
     assert np.all(np.isnan(O.solar_totals(np.linspace(0.30, 2.5, 100), rat, sol)))
     assert np.all(np.isnan(O.solar_totals(np.linspace(0.28, 2.49, 100), rat, sol)))
     assert np.all(np.isnan(O.solar_totals(np.linspace(0.28, 2.5, 100), rat, None)))
+    # the decision is taken on single-precision grid values: float32(0.28) > 0.28 still covers
+    lam32 = np.linspace(0.28, 2.5, 100).astype(np.float32)
+    assert float(lam32[0]) > 0.28 and np.all(np.isfinite(O.solar_totals(lam32, rat, sol)))
 
 
 def test_planck_obeys_wien_and_stefan_boltzmann():

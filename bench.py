@@ -53,14 +53,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profile_value(path: str, key: str):
+def profile_value(path: str, key: str, hash_key: str = "kernel_hash", source_hash=None):
     """A figure from a committed counter summary ("key: value" lines), or
-    None when the kernel sources changed since the counters were taken."""
+    None when the kernel sources changed since the counters were taken (the
+    summary's `hash_key` line against `source_hash`, by default the walk's
+    kernel_hash())."""
     try:
         kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
-    if kv.get("kernel_hash", "").strip() != kernel_hash():
+    if kv.get(hash_key, "").strip() != (kernel_hash() if source_hash is None else source_hash):
         return None
     try:
         return float(kv[key])
@@ -946,6 +948,98 @@ def weighted_main(args):
     return 0
 
 
+OUTPUT_SOURCES = ["paper_2409_00165_amd/csrc/output.hip"]
+OUTPUT_TRAFFIC = os.path.join(ROOT, "profiles", "output_stage_1e6x200_traffic.txt")
+HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
+
+
+def output_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in OUTPUT_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def output_main(args):
+    """The output stage at the design sweep's size: eq. (21) solar totals,
+    the 8 - 13 um band emittance and the colour of 10^6 spectra x 200
+    wavelengths, synthetic and resident in HBM, through fos_output_run.  A
+    step is one run over all designs; the weights are prepared once
+    beforehand.  The roofline is HBM: each design's spectrum is read once and
+    its 13 outputs written once."""
+    import torch
+    from paper_2409_00165_amd import fos
+    from paper_2409_00165_amd import workloads as W
+    t_start = time.perf_counter()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    D, L = args.output_designs, args.lambdas
+    lam = W.grid_log(0.25, 16.0, L).astype(np.float32)
+    solar, band = W.solar_standin(), (8.0, 13.0, 300.0)
+    rat = W.synthetic_rat_device(torch, D, L, seed=2409)
+    ctx = fos.Context(0)
+    h = ctx.handle
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    avail = fos.fos_output_prepare(h, lam, solar, None, band)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    tot = torch.empty(D * 4, device=dev)
+    col = torch.empty(D * 9, device=dev)
+    print(f"[bench] output stage ready: {D} designs x {L} wavelengths, available {avail}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        fos.fos_output_run(h, D, L, rat, tot, col, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fos.fos_output_run(h, D, L, rat, tot, col, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = float(np.mean(launch_ms))
+    bytes_per_design = L * 3 * 4 + (4 + 9) * 4
+    achieved = D * bytes_per_design / (ms / 1e3)
+    traffic = profile_value(OUTPUT_TRAFFIC, "traffic_bytes_per_launch", "output_hash", output_hash())
+    rec = {"metric": "output stage throughput: eq. (21) solar totals, band emittance and colour per spectrum",
+           "value": D * args.steps / wall, "unit": "spectra/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"output_stage: {D} designs x {L} wavelengths (log grid 0.25-16 um), uniform "
+                                  "R+A+T simplex draws, 5778 K solar stand-in sampled 0.28-4 um, 8-13 um band at "
+                                  "300 K, colour under equal energy"},
+           "available": avail, "prepare_seconds": t_prep,
+           "launch_ms": {"mean": ms, "min": float(np.min(launch_ms)), "max": float(np.max(launch_ms))},
+           "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK, "traffic": traffic},
+           "algorithmic_bytes_per_design": bytes_per_design, "gpu": _gpu_info(0)}
+    if not args.no_cpu_baseline:
+        from oracle import output as O
+        n = min(D, 50_000)
+        sub = rat[: n * L * 3].view(n, L, 3).cpu().numpy().astype(np.float64)
+        sol64 = (solar[0].astype(np.float64), solar[1].astype(np.float64))
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds * 2.0 / 3.0:
+            O.output_stage(lam.astype(np.float64), sub, sol64, None, band)
+            done += n
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": done / dt, "unit": "spectra/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {n} designs, repeated for {dt:.1f} s (numpy FP64, one thread)"}
+    rec["wall_s"] = time.perf_counter() - t_start
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     print("[bench] start", file=sys.stderr, flush=True)
     ap = argparse.ArgumentParser()
@@ -960,7 +1054,7 @@ def main(argv=None):
                     help="JSON fos_mc_launch overrides (the walk of the default workload; surrogate_train: the label walks)")
     ap.add_argument("--workload", default="two_species_500",
                     choices=["two_species_500", "stacks_3layer", "surrogate", "surrogate_train", "paper_context",
-                             "weighted", "optics", "valu_issue", "lone_step"],
+                             "weighted", "optics", "valu_issue", "lone_step", "output_stage"],
                     help="two_species_500 (default, the headline line; with the surrogate sweep as a sub-record), "
                          "stacks_3layer (batched sweep), surrogate (the committed ensemble: design sweep with Monte "
                          "Carlo fallback against plain Monte Carlo), surrogate_train (walk labels + training + "
@@ -969,7 +1063,8 @@ def main(argv=None):
                          "weighted (analog vs weighted-packet walk: throughput and A-estimate efficiency) or "
                          "optics (per-entry GPU Mie + effective medium: homogeneous, coated, spread) or "
                          "valu_issue (issue rates of the walk's instruction forms) or "
-                         "lone_step (step latency of a lone lane, tail phase off and on)")
+                         "lone_step (step latency of a lone lane, tail phase off and on) or "
+                         "output_stage (eq. (21) totals, band emittance and colour of 10^6 spectra)")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-photons", type=int, default=100_000)
     ap.add_argument("--epochs", type=int, default=60)
@@ -1001,6 +1096,7 @@ def main(argv=None):
     ap.add_argument("--save-model", default="", help="surrogate_train: model path (default: the committed one)")
     ap.add_argument("--model", default=MODEL_PATH, help="surrogate sweep: the ensemble to load (.fossur)")
     ap.add_argument("--designs", type=int, default=4096, help="designs of the stacks_3layer sweep")
+    ap.add_argument("--output-designs", type=int, default=1_000_000, help="designs of the output_stage leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args(argv)
@@ -1025,6 +1121,8 @@ def main(argv=None):
         return weighted_main(args)
     if args.workload == "optics":
         return optics_main(args)
+    if args.workload == "output_stage":
+        return output_main(args)
 
     import torch
     from paper_2409_00165_amd import fos

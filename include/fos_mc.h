@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define FOS_ABI_VERSION 4
+#define FOS_ABI_VERSION 5
 #define FOS_MAX_LAYERS 8
 
 /* tally slots per item, in this order, uint64 each */
@@ -469,6 +469,87 @@ fos_status fos_sweep_run(fos_ctx* ctx, const fos_mc_problem* problem, float spre
  * [lambdas] (normalised quadrature weights); out DEVICE float [2 designs]. */
 fos_status fos_spectral_reduce(fos_ctx* ctx, int32_t designs, int32_t lambdas, const float* rat, const float* w_r,
                                const float* w_e, float* out, void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Output stage                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* What a finished spectrum turns into (Output section and Results):
+ *   - the solar totals of eq. (21): R_s = int R G dlambda / int G dlambda
+ *     over the simulated range, and likewise A_s and T_s, where G is the
+ *     spectral solar irradiation.  As in the paper they exist only when a
+ *     solar spectrum is given and the grid covers at least 0.28 - 2.5 um;
+ *   - the emittance of a band (e.g. the 8 - 13 um sky window): by Kirchhoff's
+ *     law the absorptance, weighted by a blackbody spectrum at a given
+ *     temperature over the grid points inside the band (at least two);
+ *   - the colour of the reflectance spectrum, which the paper computes but
+ *     does not define.  Here: CIE 1931 XYZ under an illuminant (the
+ *     colour-matching functions from the multi-lobe analytic fit of Wyman,
+ *     Sloan and Shirley, JCGT 2013), scaled so that a perfect reflector has
+ *     Y = 1; CIE 1976 L*a*b* against the illuminant's white; and sRGB
+ *     (IEC 61966-2-1) after a Bradford adaptation of that white to D65,
+ *     linear values clipped to [0, 1] before encoding.  The grid must cover
+ *     0.38 - 0.78 um.
+ * Coverage and band membership are decided on the single-precision grid
+ * values.  Spectra are linear between their samples and zero outside them
+ * (the paper interpolates input files linearly onto the simulated grid);
+ * integrals are trapezoid sums over the grid. */
+
+/* A sampled spectrum: value[j] at um[j] micrometres.  HOST arrays, 2 <= n <=
+ * 2^20, um finite, positive and strictly increasing, value finite and >= 0.
+ * The units of value do not matter (only ratios of integrals are used). */
+typedef struct {
+    int32_t n;
+    const float* um;
+    const float* value;
+} fos_spectrum;
+
+/* What to integrate.  solar: G of eq. (21), or NULL (no solar totals).
+ * illuminant: the light the colour is seen under, or NULL (equal energy).
+ * band_temperature_k > 0 asks for the band emittance over [band_lo_um,
+ * band_hi_um] (finite, 0 < lo < hi); <= 0 leaves it out. */
+typedef struct {
+    const fos_spectrum* solar;
+    const fos_spectrum* illuminant;
+    float band_lo_um;
+    float band_hi_um;
+    float band_temperature_k;
+} fos_output_spec;
+
+#define FOS_OUTPUT_SOLAR  1   /* solar totals available           */
+#define FOS_OUTPUT_BAND   2   /* band emittance available         */
+#define FOS_OUTPUT_COLOUR 4   /* colour available                 */
+
+/* Prepare the output stage for a wavelength grid: lambda_um HOST [lambdas]
+ * (1 <= lambdas <= 2^20; finite, positive, strictly increasing), spec HOST
+ * (NULL: no solar totals, equal-energy illuminant, no band).  The context
+ * keeps five rows of quadrature weights computed on the device from the grid
+ * and the spectra, and the colour white point and matrix.  *available (HOST,
+ * may be NULL) receives the FOS_OUTPUT_* bits the grid allows.  The host
+ * arrays are copied before the call returns (it synchronises `hip_stream`).
+ * Replaces any earlier preparation; a failed call leaves the stage
+ * unprepared.  A run still in flight on another stream must finish first. */
+fos_status fos_output_prepare(fos_ctx* ctx, int32_t lambdas, const float* lambda_um, const fos_output_spec* spec,
+                              int32_t* available, void* hip_stream);
+
+/* Run the prepared stage on `designs` spectra: rat DEVICE float
+ * [designs][lambdas][3] (R, A, T per wavelength of the prepared grid;
+ * `lambdas` must equal the prepared grid's size, else FOS_E_INVALID_ARG).
+ * totals DEVICE float [designs][4] = (R_s, A_s, T_s, band emittance);
+ * colour DEVICE float [designs][9] = (X, Y, Z, L*, a*, b*, sRGB r, g, b), or
+ * NULL.  Outputs the preparation does not allow are NaN, as are solar totals
+ * when the solar spectrum has no power on the grid.  Asynchronous on
+ * `hip_stream`; FOS_E_NOT_PREPARED without a successful fos_output_prepare. */
+fos_status fos_output_run(fos_ctx* ctx, int32_t designs, int32_t lambdas, const float* rat, float* totals,
+                          float* colour, void* hip_stream);
+
+/* The prepared stage's weights, for inspection: weights DEVICE float
+ * [5][lambdas] (rows: solar, band, x, y, z; each a normalised quadrature
+ * rule, zero when that output is not available), params DEVICE float [12]
+ * (white X, Y, Z, then the 3 x 3 row-major matrix from XYZ to linear sRGB),
+ * either may be NULL; *available HOST (may be NULL).  Asynchronous copies on
+ * `hip_stream`. */
+fos_status fos_output_weights(fos_ctx* ctx, float* weights, float* params, int32_t* available, void* hip_stream);
 
 /* Measurement hook: one launch of a kernel that issues one instruction form
  * of the walk back to back on the walk's launch shape (CUs x 8 workgroups of

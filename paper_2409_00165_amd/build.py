@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfos_mc.so")
 
 SOURCES = ["mc_kernels.hip", "optics_kernels.hip", "mlp_kernels.hip", "mlp_infer.hip", "runtime.hip", "surrogate.hip",
-           "issue_kernels.hip", "tune_kernels.hip"]
+           "issue_kernels.hip", "tune_kernels.hip", "output.hip"]
 HEADERS = ["fos_device.hpp", "fos_kernels.hpp", "fos_mlp.hpp", "fos_ctx.hpp"]
 
 # Packed FP32 VALU forms are kept out of the generated code.

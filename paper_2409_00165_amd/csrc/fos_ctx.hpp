@@ -98,6 +98,11 @@ struct fos_ctx {
     size_t hand_buf_bytes = 0;
     unsigned char* graph_hand = nullptr;      // the list a captured regrouping graph uses
     unsigned long long* seed_dev = nullptr;  // device, 1 word
+    // output stage: weights [5][L], colour parameters [12], then the grid and the spectra
+    float* out_buf = nullptr;
+    size_t out_buf_bytes = 0;
+    int32_t out_lambdas = 0;                  // grid size of the prepared stage (0 = not prepared)
+    int32_t out_avail = 0;                    // FOS_OUTPUT_* bits of the prepared stage
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;

@@ -296,6 +296,7 @@ void fos_destroy(fos_ctx* c)
         if (c->tune_buf) (void)hipFree(c->tune_buf);
         if (c->hand_buf) (void)hipFree(c->hand_buf);
         if (c->seed_dev) (void)hipFree(c->seed_dev);
+        if (c->out_buf) (void)hipFree(c->out_buf);
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);

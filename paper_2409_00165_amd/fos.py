@@ -60,6 +60,20 @@ class fos_train_opts(Structure):
                 ("seed", c_uint64), ("resume", c_int32), ("loss_history", c_void_p)]
 
 
+class fos_spectrum(Structure):
+    _fields_ = [("n", c_int32), ("um", c_void_p), ("value", c_void_p)]
+
+
+class fos_output_spec(Structure):
+    _fields_ = [("solar", c_void_p), ("illuminant", c_void_p), ("band_lo_um", c_float), ("band_hi_um", c_float),
+                ("band_temperature_k", c_float)]
+
+
+OUTPUT_SOLAR, OUTPUT_BAND, OUTPUT_COLOUR = 1, 2, 4
+OUTPUT_TOTALS = ("R_s", "A_s", "T_s", "band_emittance")
+OUTPUT_COLOUR_NAMES = ("X", "Y", "Z", "L*", "a*", "b*", "sRGB_r", "sRGB_g", "sRGB_b")
+
+
 class fos_mc_launch(Structure):
     _fields_ = [("block_size", c_int32), ("refill_min", c_int32), ("chunk", c_int32),
                 ("blocks_per_cu", c_int32), ("max_steps", c_uint64), ("tail_lanes", c_int32),
@@ -147,6 +161,13 @@ def lib():
         L.fos_sweep_run.restype = c_int
         L.fos_spectral_reduce.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         L.fos_spectral_reduce.restype = c_int
+        L.fos_output_prepare.argtypes = [c_void_p, c_int32, c_void_p, POINTER(fos_output_spec), POINTER(c_int32),
+                                         c_void_p]
+        L.fos_output_prepare.restype = c_int
+        L.fos_output_run.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.fos_output_run.restype = c_int
+        L.fos_output_weights.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_int32), c_void_p]
+        L.fos_output_weights.restype = c_int
         L.fos_optics_run.argtypes = [c_void_p, POINTER(fos_optics_problem), c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]
         L.fos_optics_run.restype = c_int
@@ -532,6 +553,56 @@ def fos_spectral_reduce(ctx, designs: int, lambdas: int, rat, w_r, w_e, out, str
     _check(ctx, lib().fos_spectral_reduce(ctx, designs, lambdas, _ptr(rat, torch.float32, designs * lambdas * 3),
                                           _ptr(w_r, torch.float32, lambdas), _ptr(w_e, torch.float32, lambdas),
                                           _ptr(out, torch.float32, 2 * designs), _stream(stream)))
+
+
+def _host_f32(a):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def fos_output_prepare(ctx, lambda_um, solar=None, illuminant=None, band=None, stream=None) -> int:
+    """Prepare the output stage for the grid lambda_um (host array, um).
+    solar / illuminant: (um, value) host arrays or None; band: (lo_um,
+    hi_um, temperature_k) or None.  Returns the OUTPUT_* bits available."""
+    lam = _host_f32(lambda_um)
+    keep = [lam]
+
+    def spectrum(sp):
+        if sp is None:
+            return None
+        um, val = _host_f32(sp[0]), _host_f32(sp[1])
+        if um.shape != val.shape:
+            raise ValueError("spectrum wavelengths and values differ in length")
+        keep.extend((um, val))
+        st = fos_spectrum(um.size, um.ctypes.data_as(c_void_p), val.ctypes.data_as(c_void_p))
+        keep.append(st)
+        return ctypes.cast(ctypes.pointer(st), c_void_p)
+
+    spec = fos_output_spec(spectrum(solar), spectrum(illuminant), *(band if band is not None else (0.0, 0.0, 0.0)))
+    avail = c_int32(0)
+    _check(ctx, lib().fos_output_prepare(ctx, lam.size, lam.ctypes.data_as(c_void_p), ctypes.byref(spec),
+                                         ctypes.byref(avail), _stream(stream)))
+    return avail.value
+
+
+def fos_output_run(ctx, designs: int, lambdas: int, rat, totals, colour=None, stream=None) -> None:
+    """totals [designs, 4] and colour [designs, 9] (or None) of the spectra
+    rat [designs, lambdas, 3], all device float32 tensors."""
+    import torch
+    _check(ctx, lib().fos_output_run(ctx, designs, lambdas, _ptr(rat, torch.float32, designs * lambdas * 3),
+                                     _ptr(totals, torch.float32, designs * 4),
+                                     _ptr(colour, torch.float32, designs * 9), _stream(stream)))
+
+
+def fos_output_weights(ctx, lambdas: int, weights=None, params=None, stream=None) -> int:
+    """Copy the prepared weights [5, lambdas] and colour parameters [12]
+    into device tensors; returns the OUTPUT_* bits."""
+    import torch
+    avail = c_int32(0)
+    _check(ctx, lib().fos_output_weights(ctx, _ptr(weights, torch.float32, 5 * lambdas),
+                                         _ptr(params, torch.float32, 12),
+                                         ctypes.byref(avail), _stream(stream)))
+    return avail.value
 
 
 def parse_sur_blob(blob: bytes):

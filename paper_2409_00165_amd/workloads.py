@@ -519,6 +519,34 @@ def planck_weights(lam: np.ndarray, temperature: float, lo: float, hi: float) ->
     return w / w.sum()
 
 
+def blackbody_samples(lo_um: float, hi_um: float, step_um: float, temperature: float):
+    """A sampled spectrum in the two-column form of the paper's solar file
+    (wavelength in um, spectral power): a blackbody at `temperature` K every
+    `step_um` over [lo_um, hi_um], float32.  Stands in for a measured file
+    (AM1.5 for the solar spectrum, a daylight table for an illuminant), which
+    is not available here."""
+    um = np.round(np.arange(lo_um, hi_um + 0.5 * step_um, step_um), 6)
+    val = 1.0 / (um**5 * np.expm1(14387.769 / (um * temperature)))
+    return um.astype(np.float32), val.astype(np.float32)
+
+
+def solar_standin():
+    """The solar spectrum of the output-stage workloads: 5778 K, 0.28 - 4 um every 0.01 um."""
+    return blackbody_samples(0.28, 4.0, 0.01, 5778.0)
+
+
+def synthetic_rat_device(torch, designs: int, lambdas: int, seed: int):
+    """Seeded synthetic spectra on the GPU for the output stage: for every
+    (design, wavelength) a point drawn uniformly from the simplex
+    R + A + T = 1 (three unit-exponential draws over their sum).  Returns a
+    flat float32 CUDA tensor [designs * lambdas * 3]."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    e = torch.empty((designs * lambdas, 3), device="cuda").exponential_(generator=g)
+    e /= e.sum(1, keepdim=True)
+    return e.view(-1)
+
+
 MIE_KINDS = ("homogeneous", "coated", "spread")
 
 

@@ -51,7 +51,7 @@ def test_library_carries_gfx950_code(libpath):
 
 def test_version_and_status_strings(libpath):
     from paper_2409_00165_amd import fos
-    assert fos.fos_abi_version() == 4
+    assert fos.fos_abi_version() == 5
     assert fos.fos_status_string(0) == "FOS_OK"
     assert fos.fos_status_string(1) == "FOS_E_INVALID_ARG"
     assert fos.fos_status_string(6) == "FOS_E_NOT_PREPARED"

@@ -962,6 +962,12 @@ def output_hash() -> str:
 
 
 def output_main(args):
+    rec = output_record(args, args.steps, args.warmup, not args.no_cpu_baseline, args.copy_calibration)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def output_record(args, steps: int, warmup: int, with_cpu: bool, calibrate: bool = False) -> dict:
     """The output stage at the design sweep's size: eq. (21) solar totals,
     the 8 - 13 um band emittance and the colour of 10^6 spectra x 200
     wavelengths, synthetic and resident in HBM, through fos_output_run.  A
@@ -974,7 +980,7 @@ def output_main(args):
     t_start = time.perf_counter()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.copy_calibration:
+    if calibrate:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -994,10 +1000,10 @@ def output_main(args):
     tot = torch.empty(D * 4, device=dev)
     col = torch.empty(D * 9, device=dev)
     print(f"[bench] output stage ready: {D} designs x {L} wavelengths, available {avail}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         fos.fos_output_run(h, D, L, rat, tot, col, stream)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
@@ -1011,8 +1017,8 @@ def output_main(args):
     achieved = D * bytes_per_design / (ms / 1e3)
     traffic = profile_value(OUTPUT_TRAFFIC, "traffic_bytes_per_launch", "output_hash", output_hash())
     rec = {"metric": "output stage throughput: eq. (21) solar totals, band emittance and colour per spectrum",
-           "value": D * args.steps / wall, "unit": "spectra/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "value": D * steps / wall, "unit": "spectra/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"output_stage: {D} designs x {L} wavelengths (log grid 0.25-16 um), uniform "
                                   "R+A+T simplex draws, 5778 K solar stand-in sampled 0.28-4 um, 8-13 um band at "
@@ -1022,7 +1028,7 @@ def output_main(args):
            "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK, "traffic": traffic},
            "algorithmic_bytes_per_design": bytes_per_design, "gpu": _gpu_info(0)}
-    if not args.no_cpu_baseline:
+    if with_cpu:
         from oracle import output as O
         n = min(D, 50_000)
         sub = rat[: n * L * 3].view(n, L, 3).cpu().numpy().astype(np.float64)
@@ -1036,8 +1042,9 @@ def output_main(args):
                                "sample": f"the first {n} designs, repeated for {dt:.1f} s (numpy FP64, one thread)"}
     rec["wall_s"] = time.perf_counter() - t_start
     ctx.close()
-    print(json.dumps(rec), flush=True)
-    return 0
+    del rat, tot, col
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main(argv=None):
@@ -1077,6 +1084,7 @@ def main(argv=None):
     ap.add_argument("--mc-designs", type=int, default=4096,
                     help="designs of the sweep timed with plain Monte Carlo (the first ones)")
     ap.add_argument("--no-surrogate", action="store_true", help="leave the surrogate sub-record out")
+    ap.add_argument("--no-output-stage", action="store_true", help="leave the output-stage sub-record out")
     ap.add_argument("--tune-cache", default="", help="stacks_3layer: launch cache file of the autotuner")
     ap.add_argument("--launch-json", default="",
                     help="stacks_3layer: use this launch (JSON) instead of tuning")
@@ -1232,6 +1240,10 @@ def main(argv=None):
         t_sub = time.perf_counter()
         say = lambda m: print(f"[bench] {m} ({time.perf_counter() - t_sub:.1f} s)", file=sys.stderr, flush=True)
         rec["surrogate"] = surrogate_record(h, args, say)
+    if not args.no_output_stage:
+        # the output stage (eq. (21) totals, band emittance, colour) on 10^6 synthetic spectra
+        print("[bench] output stage ...", file=sys.stderr, flush=True)
+        rec["output_stage"] = output_record(args, 10, 2, False)
     ctx.close()
     print(json.dumps(rec), flush=True)
     return 0
